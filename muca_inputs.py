@@ -1,0 +1,60 @@
+"""Seeded synthetic inputs shared by the tests, the oracle and the benchmark.
+
+This module holds workload shapes and seeded random inputs only -- none of
+the method's arithmetic.  The multicanonical chain draws its own random
+numbers (Philox4x32-10, keyed by seed and walker), so an input here is just
+(L, walkers, seed) plus, where a test needs a nonzero weight table, a seeded
+log-weight array omega[k], k = 0..L*L.
+
+The paper's workload is the 2D Ising model itself (Sec. 3): no dataset is
+involved.  The named workloads below are the sizes the paper works at
+(L = 16, 32, 64 with O(10^4) walkers, Sec. 3.1) plus the small case an
+exhaustive enumeration can check.
+"""
+import numpy as np
+
+# Named workloads.  iter_sweeps: recorded sweeps per weight iteration;
+# iterations: fixed count (None = until flatness >= min_flat);
+# prod_sweeps: sweeps of the final production run.
+WORKLOADS = {
+    "ising_L4_W64": dict(L=4, walkers=64, iter_sweeps=2000, iterations=8, min_flat=None,
+                         prod_sweeps=20000, therm_sweeps=0),
+    "ising_L32_W16384": dict(L=32, walkers=16384, iter_sweeps=200, iterations=None,
+                             min_flat=0.5, prod_sweeps=10000, therm_sweeps=0),
+    "ising_L64_W65536": dict(L=64, walkers=65536, iter_sweeps=500, iterations=None,
+                             min_flat=0.5, prod_sweeps=10000, therm_sweeps=0),
+    "ising_L128_W16384": dict(L=128, walkers=16384, iter_sweeps=500, iterations=None,
+                              min_flat=0.5, prod_sweeps=10000, therm_sweeps=0),
+}
+
+
+def random_log_weights(L, seed, scale=2.0):
+    """Independent uniform log weights in [-scale, scale] for every bin."""
+    rng = np.random.default_rng(seed)
+    return rng.uniform(-scale, scale, size=L * L + 1).astype(np.float64)
+
+
+def smooth_log_weights(L, seed, depth=None):
+    """A smooth, bowl-shaped random log-weight profile of the kind a weight
+    iteration produces: low in the middle of the energy range, high at the
+    edges (depth ~ N ln 2 by default), plus a seeded low-frequency wiggle."""
+    N = L * L
+    rng = np.random.default_rng(seed)
+    if depth is None:
+        depth = 0.6 * N
+    u = np.linspace(-1.0, 1.0, N + 1)
+    bowl = depth * (u * u - 1.0)
+    wiggle = np.zeros(N + 1)
+    for m in range(1, 5):
+        wiggle += rng.normal(0.0, 1.0) * np.sin(np.pi * m * (u + 1.0) / 2.0)
+    return (bowl + wiggle).astype(np.float64)
+
+
+def parity_cases():
+    """(L, walkers, seed) triples for GPU-vs-oracle parity: several tiles,
+    ragged walker counts, and every lattice-shape class (L mod 4, L mod 32)."""
+    return [
+        (4, 64, 1), (4, 1, 7), (6, 65, 2), (8, 63, 3), (10, 100, 4), (12, 130, 5),
+        (16, 64, 6), (16, 257, 7), (24, 96, 8), (30, 70, 9), (32, 128, 10), (32, 4097, 11),
+        (34, 66, 12), (48, 80, 13), (64, 64, 14), (128, 65, 15),
+    ]

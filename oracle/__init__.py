@@ -1,0 +1,228 @@
+"""CPU oracle for the parallel multicanonical method -- TEST INFRASTRUCTURE.
+
+Only the test suite, the smoke check and the CPU-baseline leg of the
+benchmark may import this package.  It shares no code with the GPU library
+(``paper_1707_00919_amd``) and never imports it; the two meet only through
+``muca_inputs`` (seeded synthetic inputs, none of the method's arithmetic).
+
+Contents
+  * ``OracleMuca``     -- the walker population of Sec. 2.2 stepped by the
+                          plain C chain in ``muca_oracle.c``, with the host
+                          weight update of Eq. 4 and the production run of
+                          Sec. 3.3.
+  * ``exact_dos``      -- exact density of states of the periodic L x L Ising
+                          model: brute force, transfer matrix, and Kaufman's
+                          closed form (the ground truth named in Sec. 3).
+"""
+import ctypes
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_lib = None
+
+
+def lib():
+    """Load (building if needed) the C oracle."""
+    global _lib
+    if _lib is None:
+        path = _build.build(force=False)
+        c = ctypes.CDLL(path)
+        u8p = ctypes.POINTER(ctypes.c_int8)
+        i32p = ctypes.POINTER(ctypes.c_int32)
+        u32p = ctypes.POINTER(ctypes.c_uint32)
+        u64p = ctypes.POINTER(ctypes.c_uint64)
+        dp = ctypes.POINTER(ctypes.c_double)
+        c.oracle_philox4x32_10.argtypes = [u32p, u32p, u32p]
+        c.oracle_philox4x32_10.restype = None
+        c.oracle_draw.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint64,
+                                  ctypes.c_uint32, ctypes.c_uint32]
+        c.oracle_draw.restype = ctypes.c_uint32
+        c.oracle_energy.argtypes = [ctypes.c_int, u8p]
+        c.oracle_energy.restype = ctypes.c_int32
+        c.oracle_init.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_uint32, u8p, i32p]
+        c.oracle_init.restype = None
+        c.oracle_thresholds.argtypes = [ctypes.c_int, dp, u64p]
+        c.oracle_thresholds.restype = None
+        c.oracle_sweeps.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_uint32, u8p, i32p, u64p,
+                                    ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int, u64p,
+                                    ctypes.c_int]
+        c.oracle_sweeps.restype = None
+        c.oracle_reweight.argtypes = [ctypes.c_int, dp, u64p]
+        c.oracle_reweight.restype = None
+        c.oracle_flatness.argtypes = [ctypes.c_int, u64p]
+        c.oracle_flatness.restype = ctypes.c_double
+        c.oracle_chebyshev.argtypes = [ctypes.c_int, u64p]
+        c.oracle_chebyshev.restype = ctypes.c_double
+        c.oracle_kl_divergence.argtypes = [ctypes.c_int, u64p, ctypes.c_int]
+        c.oracle_kl_divergence.restype = ctypes.c_double
+        c.oracle_width.argtypes = [ctypes.c_int, u64p]
+        c.oracle_width.restype = ctypes.c_int
+        c.oracle_log_dos.argtypes = [ctypes.c_int, u64p, dp, ctypes.c_int, dp]
+        c.oracle_log_dos.restype = ctypes.c_int
+        _lib = c
+    return _lib
+
+
+def _p(a, ctype):
+    return a.ctypes.data_as(ctypes.POINTER(ctype))
+
+
+# ---------------------------------------------------------------- primitives
+def philox4x32_10(counter, key):
+    """Raw Philox4x32-10 block: four uint32 outputs for a 4-word counter and
+    2-word key (Salmon et al. 2011, the generator chosen in Sec. 2.3)."""
+    c = np.asarray(counter, dtype=np.uint32).copy()
+    k = np.asarray(key, dtype=np.uint32).copy()
+    out = np.zeros(4, dtype=np.uint32)
+    lib().oracle_philox4x32_10(_p(c, ctypes.c_uint32), _p(k, ctypes.c_uint32),
+                               _p(out, ctypes.c_uint32))
+    return out
+
+
+def draw(seed, walker, sweep, site, domain=0):
+    return int(lib().oracle_draw(seed, walker, sweep, site, domain))
+
+
+def energy(L, spins):
+    s = np.ascontiguousarray(spins, dtype=np.int8).reshape(-1)
+    assert s.size == L * L
+    return int(lib().oracle_energy(L, _p(s, ctypes.c_int8)))
+
+
+def thresholds(N, omega):
+    """T[(N+1), 5] uint64 for the log weights omega (Sec. 2.3 acceptance)."""
+    om = np.ascontiguousarray(omega, dtype=np.float64)
+    assert om.size == N + 1
+    t = np.zeros((N + 1) * 5, dtype=np.uint64)
+    lib().oracle_thresholds(N, _p(om, ctypes.c_double), _p(t, ctypes.c_uint64))
+    return t.reshape(N + 1, 5)
+
+
+def reweight(omega, hist):
+    """Eq. 4 in logarithmic form: omega - ln H on bins with H > 0."""
+    om = np.array(omega, dtype=np.float64)
+    h = np.ascontiguousarray(hist, dtype=np.uint64)
+    lib().oracle_reweight(om.size - 1, _p(om, ctypes.c_double), _p(h, ctypes.c_uint64))
+    return om
+
+
+def flatness(hist):
+    h = np.ascontiguousarray(hist, dtype=np.uint64)
+    return float(lib().oracle_flatness(h.size - 1, _p(h, ctypes.c_uint64)))
+
+
+def chebyshev(hist):
+    h = np.ascontiguousarray(hist, dtype=np.uint64)
+    return float(lib().oracle_chebyshev(h.size - 1, _p(h, ctypes.c_uint64)))
+
+
+def kl_divergence(hist, width_prev):
+    h = np.ascontiguousarray(hist, dtype=np.uint64)
+    return float(lib().oracle_kl_divergence(h.size - 1, _p(h, ctypes.c_uint64), width_prev))
+
+
+def width(hist):
+    h = np.ascontiguousarray(hist, dtype=np.uint64)
+    return int(lib().oracle_width(h.size - 1, _p(h, ctypes.c_uint64)))
+
+
+def log_dos(hist, omega, norm=0):
+    """ln g from a production histogram; norm 0: ln g(E_min) = ln 2,
+    norm 1: sum exp(ln g) = 2^N (Sec. 3.3).  None if the anchor is empty."""
+    h = np.ascontiguousarray(hist, dtype=np.uint64)
+    om = np.ascontiguousarray(omega, dtype=np.float64)
+    out = np.zeros(h.size, dtype=np.float64)
+    rc = lib().oracle_log_dos(h.size - 1, _p(h, ctypes.c_uint64), _p(om, ctypes.c_double),
+                              norm, _p(out, ctypes.c_double))
+    return None if rc != 0 else out
+
+
+def reachable_mask(N):
+    m = np.ones(N + 1, dtype=bool)
+    m[1] = False
+    m[N - 1] = False
+    return m
+
+
+# ---------------------------------------------------------------- the chain
+class OracleMuca:
+    """p walkers with one shared weight table (Sec. 2.2), stepped on the CPU.
+
+    Mirrors the call semantics of the GPU library: ``iterate`` runs
+    ``therm`` unrecorded sweeps, then ``sweeps`` recorded ones, sums the
+    walker histograms and applies the weight update; ``production`` does the
+    same with the weights frozen.  One sweep counter per instance, never
+    reset, labels the random numbers of every sweep.
+    """
+
+    def __init__(self, L, walkers, seed, nthreads=0):
+        if L < 4 or L % 2:
+            raise ValueError("L must be even and >= 4")
+        if walkers < 1:
+            raise ValueError("walkers must be >= 1")
+        self.L, self.W, self.seed = int(L), int(walkers), int(seed) & 0xFFFFFFFF
+        self.N = self.L * self.L
+        self.nthreads = nthreads
+        self.spins = np.zeros((self.W, self.N), dtype=np.int8)
+        self.energies = np.zeros(self.W, dtype=np.int32)
+        lib().oracle_init(self.L, self.W, self.seed, _p(self.spins, ctypes.c_int8),
+                          _p(self.energies, ctypes.c_int32))
+        self.omega = np.zeros(self.N + 1, dtype=np.float64)
+        self.hist = np.zeros(self.N + 1, dtype=np.uint64)
+        self.table = thresholds(self.N, self.omega)
+        self.sweep_counter = 0
+        self.iteration = 0
+        self.width_prev = 0
+
+    def set_log_weights(self, omega):
+        om = np.asarray(omega, dtype=np.float64)
+        if om.shape != (self.N + 1,) or not np.all(np.isfinite(om)):
+            raise ValueError("omega must be N+1 finite values")
+        self.omega = om.copy()
+
+    def _sweeps(self, nsweeps, record):
+        h = np.zeros(self.N + 1, dtype=np.uint64)
+        if nsweeps:
+            t = np.ascontiguousarray(self.table.reshape(-1))
+            lib().oracle_sweeps(self.L, self.W, self.seed, _p(self.spins, ctypes.c_int8),
+                                _p(self.energies, ctypes.c_int32), _p(t, ctypes.c_uint64),
+                                self.sweep_counter, nsweeps, 1 if record else 0,
+                                _p(h, ctypes.c_uint64), self.nthreads)
+            self.sweep_counter += nsweeps
+        return h
+
+    def _run(self, therm, sweeps):
+        self.table = thresholds(self.N, self.omega)
+        self._sweeps(therm, False)
+        self.hist = self._sweeps(sweeps, True)
+        h = self.hist
+        info = {
+            "attempts": self.W * self.N * (therm + sweeps),
+            "hist_sum": int(h.sum(dtype=np.uint64)),
+            "sweep_counter": self.sweep_counter,
+            "visited_bins": int(np.count_nonzero(h)),
+            "flatness": flatness(h),
+            "kl_divergence": kl_divergence(h, self.width_prev),
+            "chebyshev": chebyshev(h),
+        }
+        self.width_prev = width(h)
+        return info
+
+    def iterate(self, therm, sweeps):
+        info = self._run(therm, sweeps)
+        self.omega = reweight(self.omega, self.hist)
+        self.iteration += 1
+        info["iteration"] = self.iteration
+        return info
+
+    def production(self, therm, sweeps):
+        info = self._run(therm, sweeps)
+        info["iteration"] = self.iteration
+        return info
+
+    def log_dos(self, norm=0):
+        return log_dos(self.hist, self.omega, norm)
