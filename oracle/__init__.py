@@ -51,6 +51,13 @@ def lib():
                                     ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int, u64p,
                                     ctypes.c_int]
         c.oracle_sweeps.restype = None
+        c.oracle_init_ids.argtypes = [ctypes.c_int, ctypes.c_int, u32p, ctypes.c_uint32, u8p,
+                                      i32p]
+        c.oracle_init_ids.restype = None
+        c.oracle_sweeps_ids.argtypes = [ctypes.c_int, ctypes.c_int, u32p, ctypes.c_uint32, u8p,
+                                        i32p, u64p, ctypes.c_uint64, ctypes.c_uint32,
+                                        ctypes.c_int, u64p, ctypes.c_int]
+        c.oracle_sweeps_ids.restype = None
         c.oracle_reweight.argtypes = [ctypes.c_int, dp, u64p]
         c.oracle_reweight.restype = None
         c.oracle_flatness.argtypes = [ctypes.c_int, u64p]
@@ -157,11 +164,19 @@ class OracleMuca:
     walker histograms and applies the weight update; ``production`` does the
     same with the weights frozen.  One sweep counter per instance, never
     reset, labels the random numbers of every sweep.
+
+    walker_ids: run only these global walker indices (each walker's chain
+    depends on its own index alone), e.g. a sample of a large population;
+    the histogram then covers the sample only.
     """
 
-    def __init__(self, L, walkers, seed, nthreads=0):
+    def __init__(self, L, walkers, seed, nthreads=0, walker_ids=None):
         if L < 4 or L % 2:
             raise ValueError("L must be even and >= 4")
+        self.ids = None
+        if walker_ids is not None:
+            self.ids = np.ascontiguousarray(walker_ids, dtype=np.uint32)
+            walkers = self.ids.size
         if walkers < 1:
             raise ValueError("walkers must be >= 1")
         self.L, self.W, self.seed = int(L), int(walkers), int(seed) & 0xFFFFFFFF
@@ -169,14 +184,17 @@ class OracleMuca:
         self.nthreads = nthreads
         self.spins = np.zeros((self.W, self.N), dtype=np.int8)
         self.energies = np.zeros(self.W, dtype=np.int32)
-        lib().oracle_init(self.L, self.W, self.seed, _p(self.spins, ctypes.c_int8),
-                          _p(self.energies, ctypes.c_int32))
+        lib().oracle_init_ids(self.L, self.W, self._ids_ptr(), self.seed,
+                              _p(self.spins, ctypes.c_int8), _p(self.energies, ctypes.c_int32))
         self.omega = np.zeros(self.N + 1, dtype=np.float64)
         self.hist = np.zeros(self.N + 1, dtype=np.uint64)
         self.table = thresholds(self.N, self.omega)
         self.sweep_counter = 0
         self.iteration = 0
         self.width_prev = 0
+
+    def _ids_ptr(self):
+        return None if self.ids is None else _p(self.ids, ctypes.c_uint32)
 
     def set_log_weights(self, omega):
         om = np.asarray(omega, dtype=np.float64)
@@ -188,10 +206,11 @@ class OracleMuca:
         h = np.zeros(self.N + 1, dtype=np.uint64)
         if nsweeps:
             t = np.ascontiguousarray(self.table.reshape(-1))
-            lib().oracle_sweeps(self.L, self.W, self.seed, _p(self.spins, ctypes.c_int8),
-                                _p(self.energies, ctypes.c_int32), _p(t, ctypes.c_uint64),
-                                self.sweep_counter, nsweeps, 1 if record else 0,
-                                _p(h, ctypes.c_uint64), self.nthreads)
+            lib().oracle_sweeps_ids(self.L, self.W, self._ids_ptr(), self.seed,
+                                    _p(self.spins, ctypes.c_int8),
+                                    _p(self.energies, ctypes.c_int32), _p(t, ctypes.c_uint64),
+                                    self.sweep_counter, nsweeps, 1 if record else 0,
+                                    _p(h, ctypes.c_uint64), self.nthreads)
             self.sweep_counter += nsweeps
         return h
 

@@ -117,17 +117,26 @@ int32_t oracle_energy(int L, const int8_t *spins)
     return e;
 }
 
-void oracle_init(int L, int W, uint32_t seed, int8_t *spins, int32_t *energies)
+/* Initial spins and energies of n walkers; walker j carries the global index
+ * ids[j] (ids == NULL: index j), which is the second word of its key. */
+void oracle_init_ids(int L, int n, const uint32_t *ids, uint32_t seed, int8_t *spins,
+                     int32_t *energies)
 {
     int N = L * L;
-    for (int w = 0; w < W; ++w) {
-        int8_t *s = spins + (size_t)w * N;
+    for (int j = 0; j < n; ++j) {
+        uint32_t w = ids ? ids[j] : (uint32_t)j;
+        int8_t *s = spins + (size_t)j * N;
         for (int i = 0; i < N; ++i) {
-            uint32_t u = oracle_draw(seed, (uint32_t)w, 0, (uint32_t)i, 1);
+            uint32_t u = oracle_draw(seed, w, 0, (uint32_t)i, 1);
             s[i] = (u >> 31) ? 1 : -1;
         }
-        energies[w] = oracle_energy(L, s);
+        energies[j] = oracle_energy(L, s);
     }
+}
+
+void oracle_init(int L, int W, uint32_t seed, int8_t *spins, int32_t *energies)
+{
+    oracle_init_ids(L, W, NULL, seed, spins, energies);
 }
 
 /* ---------------------------------------------------------------------- */
@@ -186,9 +195,9 @@ static void walker_sweeps(int L, uint32_t seed, uint32_t walker, int8_t *s, int3
     *energy = e;
 }
 
-void oracle_sweeps(int L, int W, uint32_t seed, int8_t *spins, int32_t *energies,
-                   const uint64_t *table, uint64_t sweep0, uint32_t nsweeps, int record,
-                   uint64_t *hist, int nthreads)
+void oracle_sweeps_ids(int L, int n, const uint32_t *ids, uint32_t seed, int8_t *spins,
+                       int32_t *energies, const uint64_t *table, uint64_t sweep0,
+                       uint32_t nsweeps, int record, uint64_t *hist, int nthreads)
 {
     int N = L * L;
     int nt = 1;
@@ -199,18 +208,27 @@ void oracle_sweeps(int L, int W, uint32_t seed, int8_t *spins, int32_t *energies
 #endif
     uint64_t *partial = (uint64_t *)calloc((size_t)nt * (N + 1), sizeof(uint64_t));
 #pragma omp parallel for schedule(static) num_threads(nt)
-    for (int w = 0; w < W; ++w) {
+    for (int j = 0; j < n; ++j) {
         int tid = 0;
 #ifdef _OPENMP
         tid = omp_get_thread_num();
 #endif
-        walker_sweeps(L, seed, (uint32_t)w, spins + (size_t)w * N, energies + w, table, sweep0,
-                      nsweeps, record, partial + (size_t)tid * (N + 1));
+        uint32_t w = ids ? ids[j] : (uint32_t)j;
+        walker_sweeps(L, seed, w, spins + (size_t)j * N, energies + j, table, sweep0, nsweeps,
+                      record, partial + (size_t)tid * (N + 1));
     }
     for (int t = 0; t < nt; ++t)
         for (int k = 0; k <= N; ++k)
             hist[k] += partial[(size_t)t * (N + 1) + k];
     free(partial);
+}
+
+void oracle_sweeps(int L, int W, uint32_t seed, int8_t *spins, int32_t *energies,
+                   const uint64_t *table, uint64_t sweep0, uint32_t nsweeps, int record,
+                   uint64_t *hist, int nthreads)
+{
+    oracle_sweeps_ids(L, W, NULL, seed, spins, energies, table, sweep0, nsweeps, record, hist,
+                      nthreads);
 }
 
 /* ---------------------------------------------------------------------- */

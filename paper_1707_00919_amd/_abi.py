@@ -1,0 +1,82 @@
+"""ctypes declarations of the C ABI in include/muca.h (argument marshalling only).
+
+The product path has no fallback: if libmuca.so is missing this module
+raises, and nothing in the package computes any step of the method itself.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmuca.so")
+
+MUCA_OK = 0
+MUCA_ERR_INVALID_ARG = 1
+MUCA_ERR_OUT_OF_MEMORY = 2
+MUCA_ERR_DEVICE = 3
+MUCA_ERR_OVERFLOW = 4
+MUCA_ERR_NOT_CONVERGED = 5
+MUCA_ERR_STATE = 6
+STATUS_NAMES = {
+    0: "MUCA_OK", 1: "MUCA_ERR_INVALID_ARG", 2: "MUCA_ERR_OUT_OF_MEMORY", 3: "MUCA_ERR_DEVICE",
+    4: "MUCA_ERR_OVERFLOW", 5: "MUCA_ERR_NOT_CONVERGED", 6: "MUCA_ERR_STATE",
+}
+MUCA_MAX_L = 128
+
+
+class MucaParams(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_uint32), ("walkers", ctypes.c_uint32),
+                ("seed", ctypes.c_uint32), ("flags", ctypes.c_uint32)]
+
+
+class MucaInfo(ctypes.Structure):
+    _fields_ = [("attempts", ctypes.c_uint64), ("hist_sum", ctypes.c_uint64),
+                ("sweep_counter", ctypes.c_uint64), ("iteration", ctypes.c_uint32),
+                ("visited_bins", ctypes.c_uint32), ("flatness", ctypes.c_double),
+                ("kl_divergence", ctypes.c_double), ("chebyshev", ctypes.c_double),
+                ("kernel_ms", ctypes.c_double), ("kernel_launches", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
+
+
+_P = ctypes.c_void_p
+_SZ = ctypes.c_size_t
+_U32 = ctypes.c_uint32
+_INT = ctypes.c_int
+
+# name -> (restype, argtypes); every function declared in include/muca.h
+PROTOTYPES = {
+    "muca_state_bytes": (_SZ, [ctypes.POINTER(MucaParams)]),
+    "muca_create": (_INT, [ctypes.POINTER(MucaParams), _P, _P, _SZ, ctypes.POINTER(_P)]),
+    "muca_destroy": (_INT, [_P]),
+    "muca_iterate": (_INT, [_P, _U32, _U32, ctypes.POINTER(MucaInfo)]),
+    "muca_production": (_INT, [_P, _U32, _U32, ctypes.POINTER(MucaInfo)]),
+    "muca_histogram": (_INT, [_P, _P, _SZ]),
+    "muca_log_weights": (_INT, [_P, _P, _SZ]),
+    "muca_set_log_weights": (_INT, [_P, _P, _SZ]),
+    "muca_thresholds": (_INT, [_P, _P, _SZ]),
+    "muca_energies": (_INT, [_P, _P, _SZ]),
+    "muca_spins": (_INT, [_P, _P, _SZ]),
+    "muca_log_dos": (_INT, [_P, _INT, _P, _SZ]),
+    "muca_last_info": (_INT, [_P, ctypes.POINTER(MucaInfo)]),
+    "muca_last_error": (ctypes.c_char_p, [_P]),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libmuca.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libmuca.so not found at %s; build it with "
+                              "`python -m paper_1707_00919_amd.build`" % LIB_PATH)
+        handle = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in PROTOTYPES.items():
+            fn = getattr(handle, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = handle
+    return _lib

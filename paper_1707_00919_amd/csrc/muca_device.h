@@ -1,0 +1,66 @@
+// muca_device.h -- launch interface between the host runtime and the gfx950
+// kernels of libmuca.  Internal: not part of the public C ABI (include/muca.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace muca {
+
+// Device layout of one instance (all arrays in HBM):
+//   spins   uint32 [L * WPR][wpad]  bit x%32 of word y*WPR + x/32 is site
+//                                   (x, y); bit set = spin +1.  Word j of
+//                                   walker w lives at j*wpad + w, so the 64
+//                                   lanes of a wave touch 256 contiguous bytes.
+//   energy  int32  [wpad]
+//   hist    uint64 [N + 1]
+//   table   uint64 [(N + 1) * 4]   thresholds of the four moves that change
+//                                   the energy, slot s = m - (m > 2) for m =
+//                                   number of neighbours anti-aligned with the
+//                                   spin (m = 2 means dE = 0: always accepted).
+// wpad = walkers rounded up to a multiple of 64; the padding walkers run
+// like the others but never count into the histogram.
+constexpr uint32_t kWave = 64;
+
+struct SweepArgs {
+    uint32_t* spins;
+    int32_t* energy;
+    const uint64_t* table;
+    unsigned long long* hist;
+    uint64_t sweep0;     // instance sweep counter at the first sweep of the launch
+    uint32_t wpad;
+    uint32_t walkers;
+    uint32_t seed;
+    uint32_t nsweeps;    // sweeps of this launch
+    uint32_t therm;      // the first `therm` sweeps of the launch are not counted
+    uint32_t pad;
+};
+
+struct InitArgs {
+    uint32_t* spins;
+    int32_t* energy;
+    uint32_t L;
+    uint32_t wpad;
+    uint32_t seed;
+    uint32_t pad;
+};
+
+inline uint32_t words_per_row(uint32_t L) { return (L + 31u) / 32u; }
+inline uint32_t padded_walkers(uint32_t walkers) { return (walkers + kWave - 1) / kWave * kWave; }
+
+// Largest number of recorded sweeps one launch may run without a 32-bit LDS
+// histogram counter overflowing: 64 walkers * N attempts per sweep per bin.
+inline uint32_t max_sweeps_per_launch(uint32_t L)
+{
+    const uint64_t per_sweep = (uint64_t)kWave * L * L;
+    const uint64_t m = 0xffffffffull / per_sweep;
+    return m > 0x7fffffffull ? 0x7fffffffu : (uint32_t)m;
+}
+
+bool sweep_supported(uint32_t L);
+hipError_t launch_init(const InitArgs& a, hipStream_t s);
+hipError_t launch_sweep(uint32_t L, const SweepArgs& a, hipStream_t s);
+hipError_t launch_fill_u64(unsigned long long* p, size_t n, hipStream_t s);
+
+}  // namespace muca

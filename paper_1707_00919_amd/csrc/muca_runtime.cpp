@@ -1,0 +1,641 @@
+// muca_runtime.cpp -- host side of libmuca: the C ABI declared in
+// include/muca.h.  Owns the instance state, computes the acceptance
+// thresholds from the log weights, drives the device kernels on the
+// instance's stream, and applies the weight recursion of Eq. 4 on the host
+// (Sec. 2.2: the summed histogram defines the next weights, which are then
+// handed to every walker).
+#include "muca.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "muca_device.h"
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct Layout {
+    size_t spins_off, spins_bytes;
+    size_t energy_off, energy_bytes;
+    size_t hist_off, hist_bytes;
+    size_t table_off, table_bytes;
+    size_t total;
+};
+
+bool params_valid(const muca_params* p, std::string* why)
+{
+    if (!p) {
+        *why = "params is NULL";
+        return false;
+    }
+    if (p->L < 4 || p->L % 2 != 0 || p->L > MUCA_MAX_L) {
+        *why = "L must be even with 4 <= L <= 128";
+        return false;
+    }
+    if (!muca::sweep_supported(p->L)) {
+        *why = "no sweep kernel is built for this L";
+        return false;
+    }
+    if (p->walkers == 0) {
+        *why = "walkers must be >= 1";
+        return false;
+    }
+    if (p->walkers > (1u << 30)) {
+        *why = "walkers must be <= 2^30";
+        return false;
+    }
+    return true;
+}
+
+Layout layout_for(const muca_params* p)
+{
+    Layout l{};
+    const size_t L = p->L, N = L * L;
+    const size_t wpad = muca::padded_walkers(p->walkers);
+    const size_t words = L * muca::words_per_row(p->L);
+    size_t off = 0;
+    l.spins_off = off;
+    l.spins_bytes = words * wpad * sizeof(uint32_t);
+    off = align_up(off + l.spins_bytes);
+    l.energy_off = off;
+    l.energy_bytes = wpad * sizeof(int32_t);
+    off = align_up(off + l.energy_bytes);
+    l.hist_off = off;
+    l.hist_bytes = (N + 1) * sizeof(uint64_t);
+    off = align_up(off + l.hist_bytes);
+    l.table_off = off;
+    l.table_bytes = (N + 1) * 4 * sizeof(uint64_t);
+    off = align_up(off + l.table_bytes);
+    l.total = off;
+    return l;
+}
+
+thread_local std::string g_create_error;
+
+}  // namespace
+
+struct muca_instance {
+    muca_params p{};
+    uint32_t L = 0, N = 0, wpr = 0, wpad = 0;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    void* ws = nullptr;
+    bool own_ws = false;
+    Layout lay{};
+    uint32_t* d_spins = nullptr;
+    int32_t* d_energy = nullptr;
+    unsigned long long* d_hist = nullptr;
+    uint64_t* d_table = nullptr;
+    uint64_t* h_table4 = nullptr;  // pinned staging for the device table
+    uint64_t* h_hist = nullptr;    // pinned staging for the histogram
+    hipEvent_t ev_start = nullptr, ev_stop = nullptr;
+    std::vector<double> omega;
+    std::vector<uint64_t> table5;  // thresholds of the last sweep call
+    std::vector<uint64_t> hist;    // histogram of the last recorded call
+    uint64_t sweep_counter = 0;
+    uint32_t iteration = 0;
+    int width_prev = 0;
+    muca_info last{};
+    bool poisoned = false;
+    std::string err;
+};
+
+namespace {
+
+int fail(muca_instance* h, int code, const std::string& msg)
+{
+    if (h)
+        h->err = msg;
+    else
+        g_create_error = msg;
+    return code;
+}
+
+int device_fail(muca_instance* h, hipError_t e, const char* what)
+{
+    std::string msg = std::string(what) + ": " + hipGetErrorName(e) + " (" + hipGetErrorString(e) + ")";
+    if (h)
+        h->poisoned = true;
+    return fail(h, MUCA_ERR_DEVICE, msg);
+}
+
+#define MUCA_HIP(h, call, what)                     \
+    do {                                            \
+        hipError_t e_ = (call);                     \
+        if (e_ != hipSuccess)                       \
+            return device_fail((h), e_, (what));    \
+    } while (0)
+
+// Acceptance thresholds (Sec. 2.3 acceptance min(1, exp[omega(E') - omega(E)])
+// as an integer bound on a uint32 draw): T[k*5+d], k' = k + d - 2.
+void compute_thresholds(uint32_t N, const double* om, uint64_t* t5)
+{
+    const uint64_t always = (uint64_t)1 << 32;
+    for (uint32_t k = 0; k <= N; ++k) {
+        for (int d = 0; d < 5; ++d) {
+            const long kp = (long)k + d - 2;
+            uint64_t t = 0;
+            if (kp >= 0 && kp <= (long)N) {
+                const double diff = om[kp] - om[k];
+                if (om[kp] >= om[k])
+                    t = always;
+                else
+                    t = (uint64_t)std::floor(std::ldexp(std::exp(diff), 32));
+            }
+            t5[(size_t)k * 5 + d] = t;
+        }
+    }
+}
+
+// Device table: the four energy-changing moves per bin, ordered by the number
+// m of anti-aligned neighbours (m = 0, 1, 3, 4 <-> d = 4, 3, 1, 0).
+void device_table(uint32_t N, const uint64_t* t5, uint64_t* t4)
+{
+    static const int kDofSlot[4] = {4, 3, 1, 0};
+    for (uint32_t k = 0; k <= N; ++k)
+        for (int s = 0; s < 4; ++s)
+            t4[(size_t)k * 4 + s] = t5[(size_t)k * 5 + kDofSlot[s]];
+}
+
+bool reachable(uint32_t N, uint32_t k) { return k != 1 && k != N - 1; }
+
+double flatness_of(uint32_t N, const uint64_t* H)
+{
+    uint64_t sum = 0, mn = std::numeric_limits<uint64_t>::max();
+    for (uint32_t k = 0; k <= N; ++k) {
+        if (!reachable(N, k))
+            continue;
+        sum += H[k];
+        if (H[k] < mn)
+            mn = H[k];
+    }
+    if (sum == 0)
+        return 0.0;
+    const double mean = (double)sum / (double)(N - 1);
+    return (double)mn / mean;
+}
+
+double chebyshev_of(uint32_t N, const uint64_t* H)
+{
+    uint64_t sum = 0;
+    for (uint32_t k = 0; k <= N; ++k)
+        if (reachable(N, k))
+            sum += H[k];
+    if (sum == 0)
+        return 0.0;
+    const double m = (double)sum / (double)(N - 1);
+    double worst = 0.0;
+    for (uint32_t k = 0; k <= N; ++k) {
+        if (!reachable(N, k))
+            continue;
+        const double dev = std::fabs((double)H[k] / m - 1.0);
+        if (dev > worst)
+            worst = dev;
+    }
+    return worst;
+}
+
+double kl_of(uint32_t N, const uint64_t* H, int width_prev)
+{
+    uint64_t sum = 0;
+    for (uint32_t k = 0; k <= N; ++k)
+        sum += H[k];
+    if (sum == 0)
+        return 0.0;
+    const double w = (double)(width_prev > 10 ? width_prev : 10);
+    double dk = 0.0;
+    for (uint32_t k = 0; k <= N; ++k) {
+        if (H[k] == 0)
+            continue;
+        const double p = (double)H[k] / (double)sum;
+        dk += p * std::log(p * w);
+    }
+    return dk;
+}
+
+int width_of(uint32_t N, const uint64_t* H)
+{
+    int lo = -1, hi = -1;
+    for (uint32_t k = 0; k <= N; ++k) {
+        if (H[k] > 0) {
+            if (lo < 0)
+                lo = (int)k;
+            hi = (int)k;
+        }
+    }
+    return lo < 0 ? 0 : hi - lo + 1;
+}
+
+int check_live(const muca_instance* h)
+{
+    if (!h)
+        return MUCA_ERR_INVALID_ARG;
+    if (h->poisoned)
+        return MUCA_ERR_STATE;
+    return MUCA_OK;
+}
+
+void release(muca_instance* h)
+{
+    if (!h)
+        return;
+    if (h->stream)
+        (void)hipStreamSynchronize(h->stream);
+    if (h->ev_start)
+        (void)hipEventDestroy(h->ev_start);
+    if (h->ev_stop)
+        (void)hipEventDestroy(h->ev_stop);
+    if (h->h_table4)
+        (void)hipHostFree(h->h_table4);
+    if (h->h_hist)
+        (void)hipHostFree(h->h_hist);
+    if (h->own_ws && h->ws)
+        (void)hipFree(h->ws);
+    if (h->own_stream && h->stream)
+        (void)hipStreamDestroy(h->stream);
+    delete h;
+}
+
+// therm unrecorded sweeps, then `sweeps` recorded ones; H -> h->hist.
+int run_sweeps(muca_instance* h, uint32_t therm, uint32_t sweeps, bool update, muca_info* info)
+{
+    int rc = check_live(h);
+    if (rc != MUCA_OK)
+        return rc;
+    const uint32_t N = h->N;
+    const uint64_t total = (uint64_t)therm + sweeps;
+    const long double attempts_ld = (long double)h->p.walkers * N * (long double)total;
+    if (attempts_ld >= 18446744073709551615.0L)
+        return fail(h, MUCA_ERR_OVERFLOW, "walkers * N * sweeps exceeds 2^64");
+    if (h->sweep_counter + total < h->sweep_counter)
+        return fail(h, MUCA_ERR_OVERFLOW, "sweep counter would wrap");
+
+    compute_thresholds(N, h->omega.data(), h->table5.data());
+    device_table(N, h->table5.data(), h->h_table4);
+    MUCA_HIP(h, hipSetDevice(h->device), "hipSetDevice");
+    MUCA_HIP(h, hipMemcpyAsync(h->d_table, h->h_table4, h->lay.table_bytes, hipMemcpyHostToDevice,
+                               h->stream),
+             "threshold upload");
+    MUCA_HIP(h, muca::launch_fill_u64(h->d_hist, N + 1, h->stream), "histogram clear");
+
+    uint32_t chunk = muca::max_sweeps_per_launch(h->L);
+    const uint32_t cap = h->p.flags & MUCA_FLAG_SWEEPS_PER_LAUNCH_MASK;
+    if (cap != 0 && cap < chunk)
+        chunk = cap;
+    uint32_t launches = 0;
+    MUCA_HIP(h, hipEventRecord(h->ev_start, h->stream), "hipEventRecord");
+    for (uint64_t s0 = 0; s0 < total; s0 += chunk) {
+        const uint32_t n = (uint32_t)((total - s0) < chunk ? (total - s0) : chunk);
+        muca::SweepArgs a{};
+        a.spins = h->d_spins;
+        a.energy = h->d_energy;
+        a.table = h->d_table;
+        a.hist = h->d_hist;
+        a.sweep0 = h->sweep_counter + s0;
+        a.wpad = h->wpad;
+        a.walkers = h->p.walkers;
+        a.seed = h->p.seed;
+        a.nsweeps = n;
+        a.therm = s0 >= therm ? 0u : (uint32_t)((therm - s0) < n ? (therm - s0) : n);
+        MUCA_HIP(h, muca::launch_sweep(h->L, a, h->stream), "sweep launch");
+        ++launches;
+    }
+    MUCA_HIP(h, hipEventRecord(h->ev_stop, h->stream), "hipEventRecord");
+    MUCA_HIP(h, hipMemcpyAsync(h->h_hist, h->d_hist, h->lay.hist_bytes, hipMemcpyDeviceToHost,
+                               h->stream),
+             "histogram download");
+    MUCA_HIP(h, hipStreamSynchronize(h->stream), "sweep stream");
+    float ms = 0.0f;
+    if (launches)
+        MUCA_HIP(h, hipEventElapsedTime(&ms, h->ev_start, h->ev_stop), "hipEventElapsedTime");
+
+    h->sweep_counter += total;
+    std::memcpy(h->hist.data(), h->h_hist, h->lay.hist_bytes);
+    const uint64_t* H = h->hist.data();
+    uint64_t sum = 0;
+    uint32_t visited = 0;
+    for (uint32_t k = 0; k <= N; ++k) {
+        sum += H[k];
+        visited += H[k] > 0;
+    }
+    const uint64_t expect = (uint64_t)h->p.walkers * N * sweeps;
+    if (sum != expect) {
+        h->poisoned = true;
+        char buf[160];
+        std::snprintf(buf, sizeof buf, "histogram sum %llu != walkers*N*sweeps %llu",
+                      (unsigned long long)sum, (unsigned long long)expect);
+        return fail(h, MUCA_ERR_DEVICE, buf);
+    }
+    muca_info out{};
+    out.attempts = (uint64_t)h->p.walkers * N * total;
+    out.hist_sum = sum;
+    out.sweep_counter = h->sweep_counter;
+    out.visited_bins = visited;
+    out.flatness = flatness_of(N, H);
+    out.kl_divergence = kl_of(N, H, h->width_prev);
+    out.chebyshev = chebyshev_of(N, H);
+    out.kernel_ms = ms;
+    out.kernel_launches = launches;
+    h->width_prev = width_of(N, H);
+    if (update) {
+        // Eq. 4, W <- W / H, in logarithmic form; empty bins keep omega.
+        for (uint32_t k = 0; k <= N; ++k)
+            if (H[k] > 0)
+                h->omega[k] -= std::log((double)H[k]);
+        ++h->iteration;
+    }
+    out.iteration = h->iteration;
+    h->last = out;
+    if (info)
+        *info = out;
+    return MUCA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t muca_state_bytes(const muca_params* p)
+{
+    std::string why;
+    if (!params_valid(p, &why))
+        return 0;
+    return layout_for(p).total;
+}
+
+int muca_create(const muca_params* p, void* hip_stream, void* device_workspace,
+                size_t workspace_bytes, muca_instance** out)
+{
+    if (!out)
+        return fail(nullptr, MUCA_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    std::string why;
+    if (!params_valid(p, &why))
+        return fail(nullptr, MUCA_ERR_INVALID_ARG, why);
+    muca_instance* h = new (std::nothrow) muca_instance();
+    if (!h)
+        return fail(nullptr, MUCA_ERR_OUT_OF_MEMORY, "host allocation failed");
+    h->p = *p;
+    h->L = p->L;
+    h->N = p->L * p->L;
+    h->wpr = muca::words_per_row(p->L);
+    h->wpad = muca::padded_walkers(p->walkers);
+    h->lay = layout_for(p);
+    try {
+        h->omega.assign(h->N + 1, 0.0);
+        h->table5.assign((size_t)(h->N + 1) * 5, 0);
+        h->hist.assign(h->N + 1, 0);
+    } catch (...) {
+        delete h;
+        return fail(nullptr, MUCA_ERR_OUT_OF_MEMORY, "host allocation failed");
+    }
+
+    auto bail = [&](int code) {
+        g_create_error = h->err;
+        release(h);
+        return code;
+    };
+    hipError_t e = hipGetDevice(&h->device);
+    if (e != hipSuccess) {
+        device_fail(h, e, "hipGetDevice");
+        return bail(MUCA_ERR_DEVICE);
+    }
+    if (hip_stream) {
+        h->stream = (hipStream_t)hip_stream;
+    } else {
+        e = hipStreamCreate(&h->stream);
+        if (e != hipSuccess) {
+            device_fail(h, e, "hipStreamCreate");
+            return bail(MUCA_ERR_DEVICE);
+        }
+        h->own_stream = true;
+    }
+    if (device_workspace) {
+        if (workspace_bytes < h->lay.total || ((uintptr_t)device_workspace % kAlign) != 0) {
+            fail(h, MUCA_ERR_OUT_OF_MEMORY, "workspace too small or not 256-byte aligned");
+            return bail(MUCA_ERR_OUT_OF_MEMORY);
+        }
+        h->ws = device_workspace;
+    } else {
+        e = hipMalloc(&h->ws, h->lay.total);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            h->ws = nullptr;
+            fail(h, MUCA_ERR_OUT_OF_MEMORY, "device allocation of the instance state failed");
+            return bail(MUCA_ERR_OUT_OF_MEMORY);
+        }
+        h->own_ws = true;
+    }
+    char* base = (char*)h->ws;
+    h->d_spins = (uint32_t*)(base + h->lay.spins_off);
+    h->d_energy = (int32_t*)(base + h->lay.energy_off);
+    h->d_hist = (unsigned long long*)(base + h->lay.hist_off);
+    h->d_table = (uint64_t*)(base + h->lay.table_off);
+    if (hipHostMalloc((void**)&h->h_table4, h->lay.table_bytes, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&h->h_hist, h->lay.hist_bytes, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        fail(h, MUCA_ERR_OUT_OF_MEMORY, "pinned host allocation failed");
+        return bail(MUCA_ERR_OUT_OF_MEMORY);
+    }
+    if ((e = hipEventCreate(&h->ev_start)) != hipSuccess ||
+        (e = hipEventCreate(&h->ev_stop)) != hipSuccess) {
+        device_fail(h, e, "hipEventCreate");
+        return bail(MUCA_ERR_DEVICE);
+    }
+    muca::InitArgs ia{};
+    ia.spins = h->d_spins;
+    ia.energy = h->d_energy;
+    ia.L = h->L;
+    ia.wpad = h->wpad;
+    ia.seed = p->seed;
+    if ((e = muca::launch_init(ia, h->stream)) != hipSuccess) {
+        device_fail(h, e, "init launch");
+        return bail(MUCA_ERR_DEVICE);
+    }
+    if ((e = muca::launch_fill_u64(h->d_hist, h->N + 1, h->stream)) != hipSuccess) {
+        device_fail(h, e, "histogram clear");
+        return bail(MUCA_ERR_DEVICE);
+    }
+    if ((e = hipStreamSynchronize(h->stream)) != hipSuccess) {
+        device_fail(h, e, "init stream");
+        return bail(MUCA_ERR_DEVICE);
+    }
+    compute_thresholds(h->N, h->omega.data(), h->table5.data());
+    *out = h;
+    return MUCA_OK;
+}
+
+int muca_destroy(muca_instance* h)
+{
+    release(h);
+    return MUCA_OK;
+}
+
+int muca_iterate(muca_instance* h, uint32_t therm_sweeps, uint32_t sweeps, muca_info* info)
+{
+    return run_sweeps(h, therm_sweeps, sweeps, true, info);
+}
+
+int muca_production(muca_instance* h, uint32_t therm_sweeps, uint32_t sweeps, muca_info* info)
+{
+    return run_sweeps(h, therm_sweeps, sweeps, false, info);
+}
+
+int muca_histogram(const muca_instance* h, uint64_t* out, size_t n_bins)
+{
+    int rc = check_live(h);
+    if (rc != MUCA_OK)
+        return rc;
+    if (!out || n_bins != (size_t)h->N + 1)
+        return fail(const_cast<muca_instance*>(h), MUCA_ERR_INVALID_ARG, "n_bins must be L*L+1");
+    std::memcpy(out, h->hist.data(), n_bins * sizeof(uint64_t));
+    return MUCA_OK;
+}
+
+int muca_log_weights(const muca_instance* h, double* out, size_t n_bins)
+{
+    int rc = check_live(h);
+    if (rc != MUCA_OK)
+        return rc;
+    if (!out || n_bins != (size_t)h->N + 1)
+        return fail(const_cast<muca_instance*>(h), MUCA_ERR_INVALID_ARG, "n_bins must be L*L+1");
+    std::memcpy(out, h->omega.data(), n_bins * sizeof(double));
+    return MUCA_OK;
+}
+
+int muca_set_log_weights(muca_instance* h, const double* in, size_t n_bins)
+{
+    int rc = check_live(h);
+    if (rc != MUCA_OK)
+        return rc;
+    if (!in || n_bins != (size_t)h->N + 1)
+        return fail(h, MUCA_ERR_INVALID_ARG, "n_bins must be L*L+1");
+    for (size_t k = 0; k < n_bins; ++k)
+        if (!std::isfinite(in[k]))
+            return fail(h, MUCA_ERR_INVALID_ARG, "log weights must be finite");
+    std::memcpy(h->omega.data(), in, n_bins * sizeof(double));
+    return MUCA_OK;
+}
+
+int muca_thresholds(const muca_instance* h, uint64_t* out, size_t n)
+{
+    int rc = check_live(h);
+    if (rc != MUCA_OK)
+        return rc;
+    if (!out || n != ((size_t)h->N + 1) * 5)
+        return fail(const_cast<muca_instance*>(h), MUCA_ERR_INVALID_ARG, "n must be 5*(L*L+1)");
+    std::memcpy(out, h->table5.data(), n * sizeof(uint64_t));
+    return MUCA_OK;
+}
+
+int muca_energies(const muca_instance* h, int32_t* out, size_t walkers)
+{
+    int rc = check_live(h);
+    if (rc != MUCA_OK)
+        return rc;
+    muca_instance* m = const_cast<muca_instance*>(h);
+    if (!out || walkers != h->p.walkers)
+        return fail(m, MUCA_ERR_INVALID_ARG, "walkers must equal the instance's walker count");
+    MUCA_HIP(m, hipSetDevice(h->device), "hipSetDevice");
+    MUCA_HIP(m, hipMemcpyAsync(out, h->d_energy, walkers * sizeof(int32_t), hipMemcpyDeviceToHost,
+                               h->stream),
+             "energy download");
+    MUCA_HIP(m, hipStreamSynchronize(h->stream), "energy download");
+    return MUCA_OK;
+}
+
+int muca_spins(const muca_instance* h, int8_t* out, size_t n)
+{
+    int rc = check_live(h);
+    if (rc != MUCA_OK)
+        return rc;
+    muca_instance* m = const_cast<muca_instance*>(h);
+    const size_t N = h->N;
+    if (!out || n != (size_t)h->p.walkers * N)
+        return fail(m, MUCA_ERR_INVALID_ARG, "n must be walkers*L*L");
+    std::vector<uint32_t> words;
+    try {
+        words.resize((size_t)h->L * h->wpr * h->wpad);
+    } catch (...) {
+        return fail(m, MUCA_ERR_OUT_OF_MEMORY, "host allocation failed");
+    }
+    MUCA_HIP(m, hipSetDevice(h->device), "hipSetDevice");
+    MUCA_HIP(m, hipMemcpyAsync(words.data(), h->d_spins, words.size() * sizeof(uint32_t),
+                               hipMemcpyDeviceToHost, h->stream),
+             "spin download");
+    MUCA_HIP(m, hipStreamSynchronize(h->stream), "spin download");
+    const uint32_t L = h->L, wpr = h->wpr;
+    for (size_t w = 0; w < h->p.walkers; ++w)
+        for (uint32_t y = 0; y < L; ++y)
+            for (uint32_t x = 0; x < L; ++x) {
+                const uint32_t word = words[(size_t)(y * wpr + x / 32) * h->wpad + w];
+                out[w * N + (size_t)y * L + x] = ((word >> (x % 32)) & 1u) ? 1 : -1;
+            }
+    return MUCA_OK;
+}
+
+int muca_log_dos(const muca_instance* h, int normalization, double* out, size_t n)
+{
+    int rc = check_live(h);
+    if (rc != MUCA_OK)
+        return rc;
+    muca_instance* m = const_cast<muca_instance*>(h);
+    const uint32_t N = h->N;
+    if (!out || n != (size_t)N + 1 || (normalization != 0 && normalization != 1))
+        return fail(m, MUCA_ERR_INVALID_ARG, "n must be L*L+1 and normalization 0 or 1");
+    const uint64_t* H = h->hist.data();
+    double mx = -INFINITY;
+    for (uint32_t k = 0; k <= N; ++k) {
+        if (reachable(N, k) && H[k] > 0) {
+            out[k] = std::log((double)H[k]) - h->omega[k];
+            if (out[k] > mx)
+                mx = out[k];
+        } else {
+            out[k] = -INFINITY;
+        }
+    }
+    double c;
+    if (normalization == 0) {
+        if (H[0] == 0)
+            return fail(m, MUCA_ERR_NOT_CONVERGED, "ground-state bin is empty");
+        c = std::log(2.0) - out[0];
+    } else {
+        if (mx == -INFINITY)
+            return fail(m, MUCA_ERR_NOT_CONVERGED, "histogram is empty");
+        double s = 0.0;
+        for (uint32_t k = 0; k <= N; ++k)
+            if (out[k] != -INFINITY)
+                s += std::exp(out[k] - mx);
+        c = (double)N * std::log(2.0) - (mx + std::log(s));
+    }
+    for (uint32_t k = 0; k <= N; ++k)
+        if (out[k] != -INFINITY)
+            out[k] += c;
+    return MUCA_OK;
+}
+
+int muca_last_info(const muca_instance* h, muca_info* out)
+{
+    if (!h || !out)
+        return MUCA_ERR_INVALID_ARG;
+    *out = h->last;
+    return h->poisoned ? MUCA_ERR_STATE : MUCA_OK;
+}
+
+const char* muca_last_error(const muca_instance* h)
+{
+    return h ? h->err.c_str() : g_create_error.c_str();
+}
+
+}  // extern "C"

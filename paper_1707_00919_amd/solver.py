@@ -1,0 +1,138 @@
+"""Python face of libmuca: one ``Solver`` per multicanonical instance.
+
+Every method is a direct call into the C ABI of include/muca.h; PyTorch is
+used only to hand the library device memory (a uint8 workspace tensor) and
+the current HIP stream.  All arithmetic of the method runs in libmuca.
+"""
+import ctypes
+
+import numpy as np
+
+from . import _abi
+
+
+class MucaError(RuntimeError):
+    def __init__(self, code, message):
+        super().__init__("%s: %s" % (_abi.STATUS_NAMES.get(code, str(code)), message))
+        self.code = code
+
+
+def _ptr(a):
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+def state_bytes(L, walkers, seed=0, flags=0):
+    """Device bytes an instance holds (0 for invalid parameters)."""
+    p = _abi.MucaParams(L, walkers, seed & 0xFFFFFFFF, flags)
+    return int(_abi.lib().muca_state_bytes(ctypes.byref(p)))
+
+
+class Solver:
+    """A population of ``walkers`` independent walkers on L x L lattices that
+    share one weight table (Sec. 2.2 of the paper).
+
+    use_torch: take the workspace from torch's caching allocator and run on
+    torch's current stream (default); otherwise libmuca allocates its own
+    memory and stream.
+    """
+
+    def __init__(self, L, walkers, seed, flags=0, use_torch=True, device=None):
+        self._lib = _abi.lib()
+        self.L, self.walkers, self.seed = int(L), int(walkers), int(seed) & 0xFFFFFFFF
+        self.N = self.L * self.L
+        self._h = ctypes.c_void_p()
+        self._workspace = None
+        p = _abi.MucaParams(self.L, self.walkers, self.seed, flags)
+        nbytes = self._lib.muca_state_bytes(ctypes.byref(p))
+        stream = None
+        ws = None
+        if use_torch and nbytes:
+            import torch
+            dev = torch.device(device if device is not None else "cuda")
+            with torch.cuda.device(dev):
+                self._workspace = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+                stream = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+            ws = ctypes.c_void_p(self._workspace.data_ptr())
+        rc = self._lib.muca_create(ctypes.byref(p), stream, ws, nbytes, ctypes.byref(self._h))
+        if rc != _abi.MUCA_OK:
+            msg = self._lib.muca_last_error(None)
+            self._workspace = None
+            raise MucaError(rc, msg.decode() if msg else "")
+        self.state_bytes = int(nbytes)
+
+    # ------------------------------------------------------------- lifecycle
+    def close(self):
+        if self._h:
+            self._lib.muca_destroy(self._h)
+            self._h = ctypes.c_void_p()
+        self._workspace = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def _check(self, rc):
+        if rc != _abi.MUCA_OK:
+            msg = self._lib.muca_last_error(self._h)
+            raise MucaError(rc, msg.decode() if msg else "")
+
+    # ------------------------------------------------------------- the method
+    def iterate(self, therm_sweeps, sweeps):
+        """One weight iteration: sweeps, summed histogram, Eq. 4 update."""
+        info = _abi.MucaInfo()
+        self._check(self._lib.muca_iterate(self._h, therm_sweeps, sweeps, ctypes.byref(info)))
+        return info.as_dict()
+
+    def production(self, therm_sweeps, sweeps):
+        """Sweeps at frozen weights; replaces the stored histogram."""
+        info = _abi.MucaInfo()
+        self._check(self._lib.muca_production(self._h, therm_sweeps, sweeps, ctypes.byref(info)))
+        return info.as_dict()
+
+    # ---------------------------------------------------------------- outputs
+    def histogram(self):
+        out = np.zeros(self.N + 1, dtype=np.uint64)
+        self._check(self._lib.muca_histogram(self._h, _ptr(out), out.size))
+        return out
+
+    def log_weights(self):
+        out = np.zeros(self.N + 1, dtype=np.float64)
+        self._check(self._lib.muca_log_weights(self._h, _ptr(out), out.size))
+        return out
+
+    def set_log_weights(self, omega):
+        om = np.ascontiguousarray(omega, dtype=np.float64)
+        self._check(self._lib.muca_set_log_weights(self._h, _ptr(om), om.size))
+
+    def thresholds(self):
+        out = np.zeros((self.N + 1) * 5, dtype=np.uint64)
+        self._check(self._lib.muca_thresholds(self._h, _ptr(out), out.size))
+        return out.reshape(self.N + 1, 5)
+
+    def energies(self):
+        out = np.zeros(self.walkers, dtype=np.int32)
+        self._check(self._lib.muca_energies(self._h, _ptr(out), out.size))
+        return out
+
+    def spins(self):
+        out = np.zeros(self.walkers * self.N, dtype=np.int8)
+        self._check(self._lib.muca_spins(self._h, _ptr(out), out.size))
+        return out.reshape(self.walkers, self.N)
+
+    def log_dos(self, normalization=0):
+        out = np.zeros(self.N + 1, dtype=np.float64)
+        self._check(self._lib.muca_log_dos(self._h, normalization, _ptr(out), out.size))
+        return out
+
+    def last_info(self):
+        info = _abi.MucaInfo()
+        self._check(self._lib.muca_last_info(self._h, ctypes.byref(info)))
+        return info.as_dict()

@@ -1,0 +1,64 @@
+"""CPU-side checks of the C-ABI boundary: libmuca.so loads, exports every
+function include/muca.h declares, and rejects invalid parameters before it
+touches a device.  No compute call is made here (there is no GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1707_00919_amd import _abi
+
+ROOT = os.path.abspath(os.path.join(os.path.dirname(__file__), ".."))
+HEADER = os.path.join(ROOT, "include", "muca.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(muca_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(_abi.LIB_PATH):
+        pytest.fail("libmuca.so is not built (run __graft_entry__.build())")
+    return _abi.lib()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert len(names) >= 14
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(_abi.PROTOTYPES), "binding and header disagree"
+
+
+def test_state_bytes_sizes(lib):
+    def sb(L, W):
+        p = _abi.MucaParams(L, W, 1, 0)
+        return lib.muca_state_bytes(ctypes.byref(p))
+
+    assert sb(3, 64) == 0 and sb(2, 64) == 0 and sb(130, 64) == 0 and sb(32, 0) == 0
+    # L = 32, 16384 walkers: 2 MiB lattices + 64 KiB energies + histogram + table
+    b = sb(32, 16384)
+    assert b >= 32 * 16384 * 4 + 16384 * 4 + 1025 * 8 + 1025 * 32
+    assert b < 3 * 1024 * 1024
+    assert sb(4, 1) == sb(4, 64)            # walkers pad to a wave of 64
+
+
+def test_create_rejects_invalid_params_without_a_device(lib):
+    h = ctypes.c_void_p()
+    for L, W in [(5, 64), (2, 64), (0, 64), (130, 64), (32, 0)]:
+        p = _abi.MucaParams(L, W, 1, 0)
+        rc = lib.muca_create(ctypes.byref(p), None, None, 0, ctypes.byref(h))
+        assert rc == _abi.MUCA_ERR_INVALID_ARG
+        assert not h.value
+        assert lib.muca_last_error(None)
+    assert lib.muca_create(None, None, None, 0, ctypes.byref(h)) == _abi.MUCA_ERR_INVALID_ARG
+
+
+def test_null_handle_calls_are_rejected(lib):
+    assert lib.muca_iterate(None, 0, 1, None) == _abi.MUCA_ERR_INVALID_ARG
+    assert lib.muca_histogram(None, None, 0) == _abi.MUCA_ERR_INVALID_ARG
+    assert lib.muca_destroy(None) == _abi.MUCA_OK
