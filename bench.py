@@ -1,0 +1,238 @@
+"""Benchmark: spin-flip attempts/s and time-to-converged-weights of the
+parallel multicanonical method on one MI355X.
+
+Workload (the paper's scale, Sec. 3): 2D Ising model, L = 32 (1024 spins,
+1025 energy bins), 16384 walkers, random +-1 starts, log weights 0 at the
+start, weight iterations of 200 recorded sweeps until min H / mean H >= 0.5
+over the reachable bins, then a 10^4-sweep production run and ln g.
+
+One step = one full solve with its own seed: create the instance (initial
+spins on the device), iterate to flatness, production run, ln g.  ``value``
+is every attempted spin flip of the timed steps divided by their wall time,
+inputs resident on the device.  ``ttc_p50_s`` / ``ttc_p99_s`` are the
+nearest-rank percentiles over the timed steps of the wall time from instance
+creation to the return of the first weight iteration that reaches flatness.
+
+roofline: the sweep kernel's device time comes from HIP events the library
+records around its launches on the stream it launches them on; its
+algorithmic work per attempt is counted in VALU issue slots (see
+``ALU_SLOTS_PER_ATTEMPT``) against the chip's integer issue peak.
+
+cpu_baseline: the CPU oracle (plain C, OpenMP over walkers) on a bounded
+sample of the same workload, at the exact weights omega = -ln g.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+from muca_inputs import WORKLOADS  # noqa: E402
+
+WORKLOAD = "ising_L32_W16384"
+METRIC = "spin-flip attempts/s at L=32, 16384 walkers; p50/p99 time-to-converged-weights"
+
+# MI355X: 256 CUs x 4 SIMDs x 16 lanes at 2.4 GHz = full-rate 32-bit VALU
+# lane-operations per second.
+VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
+# Algorithmic VALU issue slots per attempt (one slot = one full-rate 32-bit
+# lane operation): a quarter of a Philox4x32-10 block (5 products 32x32->64,
+# each one quarter-rate instruction = 4 slots, and 10 two-input XORs) plus the
+# Metropolis step (4 neighbour reads, 3 adds, energy change, table address,
+# 33-bit compare, conditional flip, energy update, histogram address and
+# increment: 12 slots).
+ALU_SLOTS_PER_ATTEMPT = 5 * 4 + 10 + 12
+
+
+def nearest_rank(values, q):
+    v = sorted(values)
+    if not v:
+        return None
+    idx = max(0, min(len(v) - 1, int(math.ceil(q / 100.0 * len(v))) - 1))
+    return v[idx]
+
+
+def exact_ln_g(L):
+    path = os.path.join(ROOT, "tests", "golden", "ising_dos_L%d.txt" % L)
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        g = [int(x) for x in f if not x.startswith("#")]
+    return np.array([math.log(v) if v > 0 else -math.inf for v in g])
+
+
+def solve(Solver, wl, seed, iter_cap):
+    L, W = wl["L"], wl["walkers"]
+    t0 = time.perf_counter()
+    s = Solver(L, W, seed)
+    t_created = time.perf_counter()
+    attempts = 0
+    kernel_ms = 0.0
+    launches = 0
+    it = 0
+    converged = False
+    while it < iter_cap:
+        info = s.iterate(wl["therm_sweeps"], wl["iter_sweeps"])
+        it += 1
+        attempts += info["attempts"]
+        kernel_ms += info["kernel_ms"]
+        launches += info["kernel_launches"]
+        if info["flatness"] >= wl["min_flat"]:
+            converged = True
+            break
+    t_conv = time.perf_counter()
+    info = s.production(wl["prod_therm_sweeps"], wl["prod_sweeps"])
+    attempts += info["attempts"]
+    kernel_ms += info["kernel_ms"]
+    launches += info["kernel_launches"]
+    lng = s.log_dos(0) if converged else None
+    s.close()
+    t_end = time.perf_counter()
+    return dict(seed=seed, iterations=it, converged=converged, attempts=attempts,
+                kernel_ms=kernel_ms, launches=launches, ttc_s=t_conv - t_created,
+                wall_s=t_end - t0, ln_g=lng)
+
+
+def hardware_rate(Solver, wl, ln_g, warm_sweeps=20, timed_sweeps=200):
+    """The paper's hardware measurement (Sec. 3.1): start from the exact
+    weights, skip equilibration, time a fixed number of sweeps."""
+    L, W = wl["L"], wl["walkers"]
+    s = Solver(L, W, 12345)
+    om = np.where(np.isfinite(ln_g), -ln_g, 0.0)
+    s.set_log_weights(om)
+    s.production(0, warm_sweeps)
+    info = s.production(0, timed_sweeps)
+    s.close()
+    return info["attempts"] / (info["kernel_ms"] * 1e-3), info["kernel_ms"] / info["kernel_launches"]
+
+
+def cpu_baseline(wl, ln_g, sweeps, warm):
+    import oracle
+    L, W = wl["L"], wl["walkers"]
+    o = oracle.OracleMuca(L, W, 12345)
+    o.set_log_weights(np.where(np.isfinite(ln_g), -ln_g, 0.0))
+    o.production(0, warm)
+    t = time.perf_counter()
+    info = o.production(0, sweeps)
+    dt = time.perf_counter() - t
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
+    return {
+        "value": info["attempts"] / dt,
+        "unit": "attempts/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": "L=32, %d walkers, %d sweeps after %d warm-up sweeps at exact weights "
+                  "omega = -ln g (%.2e attempts, %.1f s)" % (W, sweeps, warm, info["attempts"], dt),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--iter-cap", type=int, default=2000)
+    ap.add_argument("--cpu-sweeps", type=int, default=40)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-hardware-rate", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the method's walkers and histogram live on a "
+              "single device in this build (--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1707_00919_amd import Solver
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    torch.cuda.set_device(0)
+    wl = WORKLOADS[WORKLOAD]
+    ln_g = exact_ln_g(wl["L"])
+
+    for i in range(args.warmup):
+        r = solve(Solver, wl, 100000 + i, args.iter_cap)
+        print("warmup step %d: %d iterations, %.2f s" % (i, r["iterations"], r["wall_s"]),
+              file=sys.stderr, flush=True)
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    runs = []
+    for i in range(args.steps):
+        r = solve(Solver, wl, 1 + i, args.iter_cap)
+        runs.append(r)
+        print("step %d: seed %d, %d iterations, ttc %.3f s, wall %.3f s" %
+              (i, r["seed"], r["iterations"], r["ttc_s"], r["wall_s"]), file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+
+    attempts = sum(r["attempts"] for r in runs)
+    kernel_ms = sum(r["kernel_ms"] for r in runs)
+    launches = sum(r["launches"] for r in runs)
+    avg_launch_s = kernel_ms * 1e-3 / launches
+    attempts_per_launch = attempts / launches
+    achieved = ALU_SLOTS_PER_ATTEMPT * attempts_per_launch / avg_launch_s
+    ttc = [r["ttc_s"] for r in runs]
+    errs = []
+    if ln_g is not None:
+        m = np.ones(wl["L"] ** 2 + 1, dtype=bool)
+        m[1] = m[-2] = False
+        for r in runs:
+            if r["ln_g"] is not None:
+                errs.append(float(np.max(np.abs(r["ln_g"][m] - ln_g[m]))))
+
+    out = {
+        "metric": METRIC,
+        "value": attempts / wall,
+        "unit": "attempts/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD, "L": wl["L"], "walkers": wl["walkers"],
+                   "iter_sweeps": wl["iter_sweeps"], "min_flatness": wl["min_flat"],
+                   "production_sweeps": wl["prod_sweeps"], "therm_sweeps": wl["therm_sweeps"],
+                   "seeds": "1..%d" % args.steps},
+        "ttc_p50_s": nearest_rank(ttc, 50),
+        "ttc_p99_s": nearest_rank(ttc, 99),
+        "iterations_p50": nearest_rank([r["iterations"] for r in runs], 50),
+        "iterations_max": max(r["iterations"] for r in runs),
+        "converged": sum(r["converged"] for r in runs),
+        "ln_g_max_abs_err": max(errs) if errs else None,
+        "sweep_kernel_attempts_per_s": attempts / (kernel_ms * 1e-3),
+        "roofline": {
+            "bound": "alu",
+            "achieved": achieved / 1e12,
+            "peak": VALU_PEAK_OPS / 1e12,
+            "unit": "Tops/s",
+            "frac": achieved / VALU_PEAK_OPS,
+            "traffic": None,
+            "kernel": "sweep_kernel<32>",
+            "avg_launch_ms": avg_launch_s * 1e3,
+            "launches": launches,
+            "slots_per_attempt": ALU_SLOTS_PER_ATTEMPT,
+        },
+    }
+    if not args.no_hardware_rate and ln_g is not None:
+        rate, ms = hardware_rate(Solver, wl, ln_g)
+        out["exact_weights_attempts_per_s"] = rate
+    if not args.no_cpu_baseline and ln_g is not None:
+        out["cpu_baseline"] = cpu_baseline(wl, ln_g, args.cpu_sweeps, 2)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -15,16 +15,22 @@ import numpy as np
 
 # Named workloads.  iter_sweeps: recorded sweeps per weight iteration;
 # iterations: fixed count (None = until flatness >= min_flat);
-# prod_sweeps: sweeps of the final production run.
+# prod_sweeps: recorded sweeps of the final production run, preceded by
+# prod_therm_sweeps unrecorded sweeps at the final weights (the walkers start
+# the production in equilibrium with the previous weights only);
+# therm_sweeps: unrecorded sweeps before each weight iteration.
 WORKLOADS = {
     "ising_L4_W64": dict(L=4, walkers=64, iter_sweeps=2000, iterations=8, min_flat=None,
-                         prod_sweeps=20000, therm_sweeps=0),
+                         prod_sweeps=20000, prod_therm_sweeps=0, therm_sweeps=0),
     "ising_L32_W16384": dict(L=32, walkers=16384, iter_sweeps=200, iterations=None,
-                             min_flat=0.5, prod_sweeps=10000, therm_sweeps=0),
+                             min_flat=0.5, prod_sweeps=10000, prod_therm_sweeps=10000,
+                             therm_sweeps=0),
     "ising_L64_W65536": dict(L=64, walkers=65536, iter_sweeps=500, iterations=None,
-                             min_flat=0.5, prod_sweeps=10000, therm_sweeps=0),
+                             min_flat=0.5, prod_sweeps=10000, prod_therm_sweeps=10000,
+                             therm_sweeps=0),
     "ising_L128_W16384": dict(L=128, walkers=16384, iter_sweeps=500, iterations=None,
-                              min_flat=0.5, prod_sweeps=10000, therm_sweeps=0),
+                              min_flat=0.5, prod_sweeps=10000, prod_therm_sweeps=10000,
+                              therm_sweeps=0),
 }
 
 

@@ -178,7 +178,7 @@ def run_workload(name, seed, max_iter=10000):
                 break
         elif info["flatness"] >= wl["min_flat"] or it >= max_iter:
             break
-    o.production(wl["therm_sweeps"], wl["prod_sweeps"])
+    o.production(wl["prod_therm_sweeps"], wl["prod_sweeps"])
     return o, it
 
 
