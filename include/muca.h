@@ -73,6 +73,15 @@ typedef enum muca_status {
  * largest count whose 32-bit on-chip histogram counters cannot overflow).   */
 #define MUCA_FLAG_DEFAULT 0u
 #define MUCA_FLAG_SWEEPS_PER_LAUNCH_MASK 0xffffu
+/* Sweep kernel choice (same results, bit for bit).  By default, for L <= 64
+ * and when no reachable threshold is 0, the split kernel runs: 32-bit
+ * thresholds and the histogram interleaved in LDS, random numbers from a
+ * second wave, the next attempt's thresholds fetched ahead.  With more than
+ * two of its workgroups (64 walkers each) per compute unit, or with FAST, the
+ * one-wave form of it runs instead; GENERIC always runs the kernel with
+ * 64-bit thresholds read from LDS (L <= 66) or L2.                           */
+#define MUCA_FLAG_GENERIC_KERNEL 0x10000u
+#define MUCA_FLAG_FAST_KERNEL 0x20000u
 
 typedef struct muca_params {
     uint32_t L;       /* even, 4 <= L <= MUCA_MAX_L                          */
@@ -94,7 +103,7 @@ typedef struct muca_info {
     double chebyshev;       /* Eq. A.1: max |H/m - 1|, m = sum H / (N-1)     */
     double kernel_ms;       /* device time of the sweep launches (HIP events) */
     uint32_t kernel_launches; /* sweep kernel launches of the call           */
-    uint32_t reserved;
+    uint32_t kernel_variant;  /* 0: generic, 1: fast, 2: split sweep kernel  */
 } muca_info;
 
 /* Device bytes an instance with these parameters holds (lattices, energies,

@@ -21,6 +21,9 @@ STATUS_NAMES = {
     4: "MUCA_ERR_OVERFLOW", 5: "MUCA_ERR_NOT_CONVERGED", 6: "MUCA_ERR_STATE",
 }
 MUCA_MAX_L = 128
+MUCA_FLAG_GENERIC_KERNEL = 0x10000
+MUCA_FLAG_FAST_KERNEL = 0x20000
+KERNEL_GENERIC, KERNEL_FAST, KERNEL_SPLIT = 0, 1, 2
 
 
 class MucaParams(ctypes.Structure):
@@ -34,10 +37,10 @@ class MucaInfo(ctypes.Structure):
                 ("visited_bins", ctypes.c_uint32), ("flatness", ctypes.c_double),
                 ("kl_divergence", ctypes.c_double), ("chebyshev", ctypes.c_double),
                 ("kernel_ms", ctypes.c_double), ("kernel_launches", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32)]
+                ("kernel_variant", ctypes.c_uint32)]
 
     def as_dict(self):
-        return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
+        return {name: getattr(self, name) for name, _ in self._fields_}
 
 
 _P = ctypes.c_void_p

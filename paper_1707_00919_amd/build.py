@@ -20,7 +20,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libmuca.so")
 ARCH = "gfx950"
 
-SOURCES = ["muca_kernels.hip", "muca_runtime.cpp"]
+SOURCES = ["muca_kernels.hip", "muca_sweep_fast.hip", "muca_sweep_split.hip", "muca_runtime.cpp"]
 COMMON = [
     "-O3", "-std=c++17", "-fPIC", "-Wall",
     "-ffp-contract=off", "-fno-fast-math",

@@ -37,6 +37,23 @@ struct SweepArgs {
     uint32_t pad;
 };
 
+// Arguments of the fast and split sweeps (L <= 64): table holds, for every bin k and
+// every count m = 0..4 of anti-aligned neighbours, S = T - 1 of the move with
+// energy change 8 - 4m at table[k*5 + m] (valid when no reachable T is 0).
+struct FastSweepArgs {
+    uint32_t* spins;
+    int32_t* energy;
+    const uint32_t* table;
+    unsigned long long* hist;
+    uint64_t sweep0;
+    uint32_t wpad;
+    uint32_t walkers;
+    uint32_t seed;
+    uint32_t nsweeps;
+    uint32_t therm;
+    uint32_t pad;
+};
+
 struct InitArgs {
     uint32_t* spins;
     int32_t* energy;
@@ -59,6 +76,10 @@ inline uint32_t max_sweeps_per_launch(uint32_t L)
 }
 
 bool sweep_supported(uint32_t L);
+bool fast_sweep_supported(uint32_t L);
+hipError_t launch_fast_sweep(uint32_t L, const FastSweepArgs& a, hipStream_t s);
+bool split_sweep_supported(uint32_t L);
+hipError_t launch_split_sweep(uint32_t L, const FastSweepArgs& a, hipStream_t s);
 hipError_t launch_init(const InitArgs& a, hipStream_t s);
 hipError_t launch_sweep(uint32_t L, const SweepArgs& a, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* p, size_t n, hipStream_t s);

@@ -15,39 +15,10 @@
 
 #include <utility>
 
+#include "philox.h"
+
 namespace muca {
 namespace {
-
-// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): the counter-based
-// generator the paper picks in Sec. 2.3.  Ten rounds of two 32x32->64 bit
-// products; the key advances by the two Weyl constants between rounds.
-constexpr uint32_t kPhiloxMulA = 0xD2511F53u;
-constexpr uint32_t kPhiloxMulB = 0xCD9E8D57u;
-constexpr uint32_t kPhiloxWeylA = 0x9E3779B9u;
-constexpr uint32_t kPhiloxWeylB = 0xBB67AE85u;
-
-struct Words4 {
-    uint32_t w[4];
-};
-
-__device__ __forceinline__ Words4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
-                                           uint32_t k0, uint32_t k1)
-{
-#pragma unroll
-    for (int round = 0; round < 10; ++round) {
-        const uint64_t pa = (uint64_t)kPhiloxMulA * c0;
-        const uint64_t pb = (uint64_t)kPhiloxMulB * c2;
-        const uint32_t n0 = (uint32_t)(pb >> 32) ^ c1 ^ k0;
-        const uint32_t n2 = (uint32_t)(pa >> 32) ^ c3 ^ k1;
-        c1 = (uint32_t)pb;
-        c3 = (uint32_t)pa;
-        c0 = n0;
-        c2 = n2;
-        k0 += kPhiloxWeylA;
-        k1 += kPhiloxWeylB;
-    }
-    return Words4{{c0, c1, c2, c3}};
-}
 
 template <int L>
 struct Shape {

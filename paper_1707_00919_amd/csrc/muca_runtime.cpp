@@ -88,6 +88,7 @@ struct muca_instance {
     muca_params p{};
     uint32_t L = 0, N = 0, wpr = 0, wpad = 0;
     int device = 0;
+    int cus = 256;  // compute units of the device
     hipStream_t stream = nullptr;
     bool own_stream = false;
     void* ws = nullptr;
@@ -166,6 +167,29 @@ void device_table(uint32_t N, const uint64_t* t5, uint64_t* t4)
     for (uint32_t k = 0; k <= N; ++k)
         for (int s = 0; s < 4; ++s)
             t4[(size_t)k * 4 + s] = t5[(size_t)k * 5 + kDofSlot[s]];
+}
+
+// Fast-kernel table: S = T - 1 as uint32 for every move out of bin k, indexed
+// by the count m = 0..4 of anti-aligned neighbours (d = 4 - m).  Moves whose
+// target lies outside 0..N are never proposed (the lattice always matches its
+// energy) and get 0.  Returns false when a move that can be proposed has T = 0:
+// r <= T - 1 cannot express "never", so the generic kernel must run.
+bool fast_table(uint32_t N, const uint64_t* t5, uint32_t* f)
+{
+    for (uint32_t k = 0; k <= N; ++k) {
+        for (int m = 0; m < 5; ++m) {
+            const long kp = (long)k + 2 - m;
+            const uint64_t t = t5[(size_t)k * 5 + (4 - m)];
+            if (kp < 0 || kp > (long)N) {
+                f[(size_t)k * 5 + m] = 0u;
+                continue;
+            }
+            if (t == 0)
+                return false;
+            f[(size_t)k * 5 + m] = (uint32_t)(t - 1);
+        }
+    }
+    return true;
 }
 
 bool reachable(uint32_t N, uint32_t k) { return k != 1 && k != N - 1; }
@@ -282,7 +306,25 @@ int run_sweeps(muca_instance* h, uint32_t therm, uint32_t sweeps, bool update, m
         return fail(h, MUCA_ERR_OVERFLOW, "sweep counter would wrap");
 
     compute_thresholds(N, h->omega.data(), h->table5.data());
-    device_table(N, h->table5.data(), h->h_table4);
+    // kernel choice: 2 split, 1 fast, 0 generic (all give the same bits)
+    uint32_t variant = 0;
+    if (!(h->p.flags & MUCA_FLAG_GENERIC_KERNEL) &&
+        (muca::split_sweep_supported(h->L) || muca::fast_sweep_supported(h->L)) &&
+        fast_table(N, h->table5.data(), reinterpret_cast<uint32_t*>(h->h_table4))) {
+        // The split kernel gives each 64 walkers a second wave for the random
+        // numbers; once more than two of its workgroups share a CU those waves
+        // compete with the chains for issue slots and the one-wave form wins.
+        const bool want_fast = (h->p.flags & MUCA_FLAG_FAST_KERNEL) != 0 ||
+                               (h->wpad / muca::kWave > 2u * (uint32_t)h->cus &&
+                                muca::fast_sweep_supported(h->L));
+        if (muca::split_sweep_supported(h->L) && !(want_fast && muca::fast_sweep_supported(h->L)))
+            variant = 2;
+        else
+            variant = 1;
+    }
+    const bool fast = variant != 0;
+    if (!fast)
+        device_table(N, h->table5.data(), h->h_table4);
     MUCA_HIP(h, hipSetDevice(h->device), "hipSetDevice");
     MUCA_HIP(h, hipMemcpyAsync(h->d_table, h->h_table4, h->lay.table_bytes, hipMemcpyHostToDevice,
                                h->stream),
@@ -297,18 +339,37 @@ int run_sweeps(muca_instance* h, uint32_t therm, uint32_t sweeps, bool update, m
     MUCA_HIP(h, hipEventRecord(h->ev_start, h->stream), "hipEventRecord");
     for (uint64_t s0 = 0; s0 < total; s0 += chunk) {
         const uint32_t n = (uint32_t)((total - s0) < chunk ? (total - s0) : chunk);
-        muca::SweepArgs a{};
-        a.spins = h->d_spins;
-        a.energy = h->d_energy;
-        a.table = h->d_table;
-        a.hist = h->d_hist;
-        a.sweep0 = h->sweep_counter + s0;
-        a.wpad = h->wpad;
-        a.walkers = h->p.walkers;
-        a.seed = h->p.seed;
-        a.nsweeps = n;
-        a.therm = s0 >= therm ? 0u : (uint32_t)((therm - s0) < n ? (therm - s0) : n);
-        MUCA_HIP(h, muca::launch_sweep(h->L, a, h->stream), "sweep launch");
+        const uint32_t th = s0 >= therm ? 0u : (uint32_t)((therm - s0) < n ? (therm - s0) : n);
+        if (fast) {
+            muca::FastSweepArgs a{};
+            a.spins = h->d_spins;
+            a.energy = h->d_energy;
+            a.table = reinterpret_cast<const uint32_t*>(h->d_table);
+            a.hist = h->d_hist;
+            a.sweep0 = h->sweep_counter + s0;
+            a.wpad = h->wpad;
+            a.walkers = h->p.walkers;
+            a.seed = h->p.seed;
+            a.nsweeps = n;
+            a.therm = th;
+            MUCA_HIP(h,
+                     variant == 2 ? muca::launch_split_sweep(h->L, a, h->stream)
+                                  : muca::launch_fast_sweep(h->L, a, h->stream),
+                     "sweep launch");
+        } else {
+            muca::SweepArgs a{};
+            a.spins = h->d_spins;
+            a.energy = h->d_energy;
+            a.table = h->d_table;
+            a.hist = h->d_hist;
+            a.sweep0 = h->sweep_counter + s0;
+            a.wpad = h->wpad;
+            a.walkers = h->p.walkers;
+            a.seed = h->p.seed;
+            a.nsweeps = n;
+            a.therm = th;
+            MUCA_HIP(h, muca::launch_sweep(h->L, a, h->stream), "sweep launch");
+        }
         ++launches;
     }
     MUCA_HIP(h, hipEventRecord(h->ev_stop, h->stream), "hipEventRecord");
@@ -347,6 +408,7 @@ int run_sweeps(muca_instance* h, uint32_t therm, uint32_t sweeps, bool update, m
     out.chebyshev = chebyshev_of(N, H);
     out.kernel_ms = ms;
     out.kernel_launches = launches;
+    out.kernel_variant = variant;
     h->width_prev = width_of(N, H);
     if (update) {
         // Eq. 4, W <- W / H, in logarithmic form; empty bins keep omega.
@@ -409,6 +471,11 @@ int muca_create(const muca_params* p, void* hip_stream, void* device_workspace,
     hipError_t e = hipGetDevice(&h->device);
     if (e != hipSuccess) {
         device_fail(h, e, "hipGetDevice");
+        return bail(MUCA_ERR_DEVICE);
+    }
+    e = hipDeviceGetAttribute(&h->cus, hipDeviceAttributeMultiprocessorCount, h->device);
+    if (e != hipSuccess) {
+        device_fail(h, e, "hipDeviceGetAttribute");
         return bail(MUCA_ERR_DEVICE);
     }
     if (hip_stream) {

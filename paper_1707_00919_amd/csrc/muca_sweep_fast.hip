@@ -1,0 +1,285 @@
+// muca_sweep_fast.hip -- the multicanonical Metropolis sweep for lattices whose
+// whole per-bin state fits in LDS (L <= 64), tuned for gfx950.
+//
+// Same chain as the generic sweep (Sec. 2.3: one lane per walker, all lanes on
+// the same site in typewriter order, Philox draws labelled by walker and site,
+// acceptance min(1, exp[omega(E') - omega(E)]) as an integer threshold), with
+// the per-attempt work cut to what the method needs:
+//
+//  * Bond words.  At the start of a row the lane forms, for the row's sites,
+//    the mismatch with the row above (already updated) and below (not yet),
+//    and a word nb whose bit i says whether sites i and i+1 of the row differ.
+//    nb is kept current as spins flip (a flip of site x toggles bits x-1 and
+//    x), so the number m of anti-aligned neighbours of site x is a popcount
+//    of two nb bits plus two single-bit extracts.  The flipped sites of the
+//    row are recovered from the change of nb at the end of the row.
+//  * One LDS record of 28 bytes per energy bin k: the five thresholds of the
+//    moves out of k, ordered by m, the bin's histogram counter and a pad word
+//    (an odd word stride spreads the gathers of a wave over all LDS banks).
+//    A walker keeps a single byte address z = 28k + 8: the threshold of a
+//    move with m anti-aligned neighbours sits at z + 4(m - 2), the record of
+//    the target bin k' = k + 2 - m at z - 28(m - 2), and the counter at
+//    z + 12.
+//  * Thresholds are stored as S = T - 1 in 32 bits and an attempt is accepted
+//    iff r <= S, which equals r < T for every T in [1, 2^32].  The host uses
+//    this kernel only when no reachable threshold is 0 (then r < T can never
+//    hold); otherwise it runs the generic kernel with 64-bit thresholds.
+//  * The Philox block of the next four sites is computed while the current
+//    four attempts wait on LDS.
+#include "muca_device.h"
+
+#include <utility>
+
+#include "philox.h"
+
+namespace muca {
+namespace {
+
+template <int L>
+struct FastShape {
+    static constexpr int N = L * L;
+    static constexpr int WPR = (L + 31) / 32;
+    static constexpr int LAST = L - 32 * (WPR - 1);  // sites in the last word of a row
+    static constexpr int RPS = (L % 4 == 0) ? 1 : 2;  // rows per loop step: whole Philox blocks
+    static constexpr int BLOCKS = RPS * L / 4;        // Philox blocks per loop step
+    static constexpr int REC = 28;                    // LDS bytes per energy bin
+    static constexpr int LDS_BYTES = REC * (N + 1);
+};
+
+template <int L>
+struct FastState {
+    static constexpr int WPR = FastShape<L>::WPR;
+    uint32_t up[WPR];   // row y-1, already updated in this sweep
+    uint32_t cur[WPR];  // row y as it was when the row started
+    uint32_t dn[WPR];   // row y+1, not yet updated
+    uint32_t u[WPR];    // cur ^ up: site differs from the site above
+    uint32_t d[WPR];    // cur ^ dn: site differs from the site below
+    uint32_t nb[WPR];   // bit i: site i differs from site i+1 (cyclic), current
+    uint32_t nb0[WPR];  // nb when the row started
+    uint32_t f0;        // 1 if site 0 of the row flipped
+};
+
+struct FastCtx {
+    uint32_t blk0;   // Philox block of the first site of the loop step
+    uint32_t c1, c2; // sweep counter words
+    uint32_t seed, walker;
+    uint32_t inc;    // 1 if this sweep is recorded and the walker is live
+};
+
+__device__ __forceinline__ uint32_t lds_load(const uint8_t* lds, uint32_t byte)
+{
+    return *reinterpret_cast<const uint32_t*>(lds + byte);
+}
+
+// Row start: mismatch words and the cyclic neighbour-difference word nb.
+template <int L>
+__device__ __forceinline__ void row_begin(FastState<L>& st)
+{
+    using S = FastShape<L>;
+#pragma unroll
+    for (int w = 0; w < S::WPR; ++w) {
+        st.u[w] = st.cur[w] ^ st.up[w];
+        st.d[w] = st.cur[w] ^ st.dn[w];
+        uint32_t next;  // bit i = site i+1 of the row (cyclic)
+        if (w + 1 < S::WPR)
+            next = (st.cur[w] >> 1) | (st.cur[w + 1] << 31);
+        else
+            next = (st.cur[w] >> 1) | ((st.cur[0] & 1u) << (S::LAST - 1));
+        st.nb[w] = st.cur[w] ^ next;
+        st.nb0[w] = st.nb[w];
+    }
+}
+
+// Row end: the flipped sites F solve F_i ^ F_{i+1} = (nb0 ^ nb)_i with F_0 = f0.
+template <int L>
+__device__ __forceinline__ void row_end(FastState<L>& st)
+{
+    using S = FastShape<L>;
+    uint32_t carry = 0u - st.f0;  // all ones if site 0 flipped
+#pragma unroll
+    for (int w = 0; w < S::WPR; ++w) {
+        uint32_t p = st.nb0[w] ^ st.nb[w];
+        p ^= p << 1;
+        p ^= p << 2;
+        p ^= p << 4;
+        p ^= p << 8;
+        p ^= p << 16;  // inclusive prefix xor within the word
+        uint32_t flips = (p << 1) ^ carry;
+        if (w + 1 == S::WPR && S::LAST < 32)
+            flips &= (1u << S::LAST) - 1u;
+        carry ^= 0u - (p >> 31);
+        st.cur[w] ^= flips;
+    }
+}
+
+template <int L, int P>
+__device__ __forceinline__ void fast_attempt(FastState<L>& st, uint32_t& z, Words4& rcur,
+                                             Words4& rnext, const FastCtx& c, uint8_t* lds)
+{
+    using S = FastShape<L>;
+    constexpr int X = P % L;
+    constexpr int W = X >> 5, B = X & 31;
+    constexpr int XL = (X + L - 1) % L;
+    constexpr int WL = XL >> 5, BL = XL & 31;
+    if constexpr ((P & 3) == 0) {
+        rcur = rnext;
+        if constexpr ((P >> 2) + 1 < S::BLOCKS)
+            rnext = philox10(c.blk0 + (uint32_t)((P >> 2) + 1), c.c1, c.c2, 0u, c.seed, c.walker);
+    }
+    const uint32_t r = rcur.w[P & 3];
+    // ms = (anti-aligned neighbours) - 2 = -(change of the energy bin)
+    const int vert = (int)((st.u[W] >> B) & 1u) + (int)((st.d[W] >> B) & 1u) - 2;
+    int ms;
+    if constexpr (WL == W)
+        ms = __builtin_popcount(st.nb[W] & ((1u << BL) | (1u << B))) + vert;
+    else
+        ms = __builtin_popcount(st.nb[WL] & (1u << BL)) + __builtin_popcount(st.nb[W] & (1u << B)) +
+             vert;
+    const uint32_t thr = lds_load(lds, z + (uint32_t)(ms * 4));
+    const uint32_t target = z - (uint32_t)(ms * 28);
+    const bool accept = r <= thr;
+    z = accept ? target : z;
+    if constexpr (WL == W) {
+        constexpr uint32_t M = (1u << BL) | (1u << B);
+        st.nb[W] = accept ? (st.nb[W] ^ M) : st.nb[W];
+    } else {
+        st.nb[WL] = accept ? (st.nb[WL] ^ (1u << BL)) : st.nb[WL];
+        st.nb[W] = accept ? (st.nb[W] ^ (1u << B)) : st.nb[W];
+    }
+    if constexpr (X == 0)
+        st.f0 = accept ? 1u : 0u;
+    atomicAdd(reinterpret_cast<uint32_t*>(lds + z + 12), c.inc);
+}
+
+template <int L, int RR, int... Xs>
+__device__ __forceinline__ void fast_row_sites(FastState<L>& st, uint32_t& z, Words4& rcur,
+                                               Words4& rnext, const FastCtx& c, uint8_t* lds,
+                                               std::integer_sequence<int, Xs...>)
+{
+    (fast_attempt<L, RR * L + Xs>(st, z, rcur, rnext, c, lds), ...);
+}
+
+template <int L, int RR>
+__device__ __forceinline__ void fast_row_step(FastState<L>& st, uint32_t& z, Words4& rcur,
+                                              Words4& rnext, const FastCtx& c, uint8_t* lds,
+                                              uint32_t* mine, size_t stride, int y)
+{
+    constexpr int WPR = FastShape<L>::WPR;
+    const int yy = y + RR;
+    const int ynext = (yy + 2) % L;
+    uint32_t nx[WPR];
+#pragma unroll
+    for (int j = 0; j < WPR; ++j)
+        nx[j] = mine[(size_t)(ynext * WPR + j) * stride];
+    row_begin<L>(st);
+    fast_row_sites<L, RR>(st, z, rcur, rnext, c, lds, std::make_integer_sequence<int, L>{});
+    row_end<L>(st);
+#pragma unroll
+    for (int j = 0; j < WPR; ++j) {
+        mine[(size_t)(yy * WPR + j) * stride] = st.cur[j];
+        st.up[j] = st.cur[j];
+        st.cur[j] = st.dn[j];
+        st.dn[j] = nx[j];
+    }
+}
+
+template <int L>
+__global__ __launch_bounds__(64) void sweep_fast_kernel(FastSweepArgs a)
+{
+    using S = FastShape<L>;
+    constexpr int N = S::N;
+    constexpr int WPR = S::WPR;
+    __shared__ __attribute__((aligned(16))) uint8_t lds[S::LDS_BYTES];
+
+    const uint32_t lane = threadIdx.x;
+    const uint32_t w = blockIdx.x * kWave + lane;
+
+    // records: five thresholds S = T - 1 (by m), a zeroed histogram counter, pad
+    uint32_t* rec = reinterpret_cast<uint32_t*>(lds);
+    for (int i = lane; i < 7 * (N + 1); i += kWave) {
+        const int k = i / 7, j = i - 7 * (i / 7);
+        rec[i] = j < 5 ? a.table[k * 5 + j] : 0u;
+    }
+    __syncthreads();
+
+    uint32_t* const mine = a.spins + w;
+    const size_t stride = a.wpad;
+    FastState<L> st;
+#pragma unroll
+    for (int j = 0; j < WPR; ++j) {
+        st.up[j] = mine[(size_t)((L - 1) * WPR + j) * stride];
+        st.cur[j] = mine[(size_t)j * stride];
+        st.dn[j] = mine[(size_t)(WPR + j) * stride];
+    }
+    st.f0 = 0u;
+    const int k0 = (a.energy[w] + 2 * N) >> 2;
+    uint32_t z = 28u * (uint32_t)k0 + 8u;
+    const uint32_t live = w < a.walkers ? 1u : 0u;
+
+    FastCtx c;
+    c.seed = a.seed;
+    c.walker = w;
+    for (uint32_t t = 0; t < a.nsweeps; ++t) {
+        const uint64_t sweep = a.sweep0 + t;
+        c.c1 = (uint32_t)sweep;
+        c.c2 = (uint32_t)(sweep >> 32);
+        c.inc = t >= a.therm ? live : 0u;
+        for (int y = 0; y < L; y += S::RPS) {
+            c.blk0 = (uint32_t)(y * L) >> 2;
+            Words4 rcur;
+            Words4 rnext = philox10(c.blk0, c.c1, c.c2, 0u, c.seed, c.walker);
+            fast_row_step<L, 0>(st, z, rcur, rnext, c, lds, mine, stride, y);
+            if constexpr (S::RPS == 2)
+                fast_row_step<L, 1>(st, z, rcur, rnext, c, lds, mine, stride, y);
+        }
+    }
+    a.energy[w] = 4 * (int)((z - 8u) / 28u) - 2 * N;
+
+    __syncthreads();
+    for (int k = lane; k <= N; k += kWave) {
+        const uint32_t v = rec[7 * k + 5];
+        if (v)
+            atomicAdd(a.hist + k, (unsigned long long)v);
+    }
+}
+
+template <int L>
+hipError_t launch_fast_L(const FastSweepArgs& a, hipStream_t s)
+{
+    hipLaunchKernelGGL(sweep_fast_kernel<L>, dim3(a.wpad / kWave), dim3(kWave), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+#define MUCA_FAST_L(X)                                                                        \
+    X(4) X(6) X(8) X(10) X(12) X(14) X(16) X(18) X(20) X(22) X(24) X(26) X(28) X(30) X(32)    \
+    X(34) X(36) X(38) X(40) X(42) X(44) X(46) X(48) X(50) X(52) X(54) X(56) X(58) X(60) X(62) \
+    X(64)
+
+bool fast_sweep_supported(uint32_t L)
+{
+    switch (L) {
+#define MUCA_CASE(LL) case LL:
+        MUCA_FAST_L(MUCA_CASE)
+#undef MUCA_CASE
+        return true;
+    default:
+        return false;
+    }
+}
+
+hipError_t launch_fast_sweep(uint32_t L, const FastSweepArgs& a, hipStream_t s)
+{
+    switch (L) {
+#define MUCA_CASE(LL) \
+    case LL:          \
+        return launch_fast_L<LL>(a, s);
+        MUCA_FAST_L(MUCA_CASE)
+#undef MUCA_CASE
+    default:
+        return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace muca

@@ -109,6 +109,48 @@ def test_small_workload_end_to_end():
     assert np.max(np.abs(s.log_dos(0)[m] - exact[m])) < 0.02
 
 
+@pytest.mark.parametrize("L,W,seed", [(4, 64, 1), (6, 65, 2), (16, 257, 7), (30, 70, 9),
+                                      (32, 4097, 11), (34, 66, 12), (48, 80, 13), (62, 65, 3),
+                                      (64, 64, 14)])
+def test_kernel_variants_agree(L, W, seed):
+    # split (two waves, thresholds fetched ahead), fast (one wave) and generic
+    # (64-bit thresholds) sweep kernels: the same bits, and the oracle's
+    from paper_1707_00919_amd import _abi
+    note("kernel variants L=%d W=%d seed=%d" % (L, W, seed))
+    o = oracle.OracleMuca(L, W, seed)
+    runs = [(Solver(L, W, seed), 2 if L != 62 else 1),
+            (Solver(L, W, seed, flags=_abi.MUCA_FLAG_FAST_KERNEL), 1),
+            (Solver(L, W, seed, flags=_abi.MUCA_FLAG_GENERIC_KERNEL), 0)]
+    om = smooth_log_weights(L, seed + 100)
+    o.set_log_weights(om)
+    oi = o.iterate(2, 3)
+    for s, variant in runs:
+        s.set_log_weights(om)
+        si = s.iterate(2, 3)
+        assert si["kernel_variant"] == variant
+        assert_call(si, oi, s, o)
+        assert_state(s, o)
+
+
+def test_zero_threshold_falls_back_to_generic_kernel():
+    # a weight drop of 30 between neighbouring bins makes a reachable
+    # threshold 0, which the 32-bit form cannot hold: the call must run the
+    # generic kernel and still match the oracle
+    note("zero-threshold fallback")
+    L, W, seed = 8, 64, 4
+    om = random_log_weights(L, 4, scale=1.0)
+    om[30:] -= 30.0
+    s = Solver(L, W, seed)
+    o = oracle.OracleMuca(L, W, seed)
+    s.set_log_weights(om)
+    o.set_log_weights(om)
+    assert oracle.thresholds(L * L, om)[29, 3] == 0
+    si = s.production(1, 3)
+    assert si["kernel_variant"] == 0
+    assert_call(si, o.production(1, 3), s, o)
+    assert_state(s, o)
+
+
 @pytest.mark.parametrize("cap", [1, 3])
 def test_launch_split_does_not_change_results(cap):
     note("launch split cap=%d" % cap)
