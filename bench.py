@@ -15,8 +15,8 @@ creation to the return of the first weight iteration that reaches flatness.
 
 roofline: the sweep kernel's device time comes from HIP events the library
 records around its launches on the stream it launches them on; its
-algorithmic work per attempt is counted in VALU issue slots (see
-``ALU_SLOTS_PER_ATTEMPT``) against the chip's integer issue peak.
+algorithmic work per attempt is counted in 32-bit integer operations (see
+``ALU_OPS_PER_ATTEMPT``) against the chip's integer issue peak.
 
 cpu_baseline: the CPU oracle (plain C, OpenMP over walkers) on a bounded
 sample of the same workload, at the exact weights omega = -ln g.
@@ -40,15 +40,15 @@ WORKLOAD = "ising_L32_W16384"
 METRIC = "spin-flip attempts/s at L=32, 16384 walkers; p50/p99 time-to-converged-weights"
 
 # MI355X: 256 CUs x 4 SIMDs x 16 lanes at 2.4 GHz = full-rate 32-bit VALU
-# lane-operations per second.
+# lane-operations per second.  On gfx950 the 32-bit integer multiplies
+# (lo, hi and the 32x32->64 mad) issue at the same rate as an add.
 VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
-# Algorithmic VALU issue slots per attempt (one slot = one full-rate 32-bit
-# lane operation): a quarter of a Philox4x32-10 block (5 products 32x32->64,
-# each one quarter-rate instruction = 4 slots, and 10 two-input XORs) plus the
-# Metropolis step (4 neighbour reads, 3 adds, energy change, table address,
-# 33-bit compare, conditional flip, energy update, histogram address and
-# increment: 12 slots).
-ALU_SLOTS_PER_ATTEMPT = 5 * 4 + 10 + 12
+# Algorithmic 32-bit integer operations per attempt: a quarter of a
+# Philox4x32-10 block (5 products 32x32->64 and 10 two-input XORs; the key
+# schedule is per walker and precomputed) plus the Metropolis step (4
+# neighbour reads, 3 adds, the energy change, the table index, the compare,
+# the conditional flip, the energy update, the histogram increment: 13).
+ALU_OPS_PER_ATTEMPT = 5 + 10 + 13
 
 
 def nearest_rank(values, q):
@@ -68,6 +68,9 @@ def exact_ln_g(L):
     return np.array([math.log(v) if v > 0 else -math.inf for v in g])
 
 
+KERNEL_NAMES = {0: "sweep_kernel", 1: "sweep_fast_kernel", 2: "sweep_split_kernel"}
+
+
 def solve(Solver, wl, seed, iter_cap):
     L, W = wl["L"], wl["walkers"]
     t0 = time.perf_counter()
@@ -76,28 +79,33 @@ def solve(Solver, wl, seed, iter_cap):
     attempts = 0
     kernel_ms = 0.0
     launches = 0
+    variant_ms = {}
     it = 0
     converged = False
-    while it < iter_cap:
-        info = s.iterate(wl["therm_sweeps"], wl["iter_sweeps"])
-        it += 1
+
+    def account(info):
+        nonlocal attempts, kernel_ms, launches
         attempts += info["attempts"]
         kernel_ms += info["kernel_ms"]
         launches += info["kernel_launches"]
+        v = info["kernel_variant"]
+        variant_ms[v] = variant_ms.get(v, 0.0) + info["kernel_ms"]
+
+    while it < iter_cap:
+        info = s.iterate(wl["therm_sweeps"], wl["iter_sweeps"])
+        it += 1
+        account(info)
         if info["flatness"] >= wl["min_flat"]:
             converged = True
             break
     t_conv = time.perf_counter()
-    info = s.production(wl["prod_therm_sweeps"], wl["prod_sweeps"])
-    attempts += info["attempts"]
-    kernel_ms += info["kernel_ms"]
-    launches += info["kernel_launches"]
+    account(s.production(wl["prod_therm_sweeps"], wl["prod_sweeps"]))
     lng = s.log_dos(0) if converged else None
     s.close()
     t_end = time.perf_counter()
     return dict(seed=seed, iterations=it, converged=converged, attempts=attempts,
-                kernel_ms=kernel_ms, launches=launches, ttc_s=t_conv - t_created,
-                wall_s=t_end - t0, ln_g=lng)
+                kernel_ms=kernel_ms, launches=launches, variant_ms=variant_ms,
+                ttc_s=t_conv - t_created, wall_s=t_end - t0, ln_g=lng)
 
 
 def hardware_rate(Solver, wl, ln_g, warm_sweeps=20, timed_sweeps=200):
@@ -111,6 +119,58 @@ def hardware_rate(Solver, wl, ln_g, warm_sweeps=20, timed_sweeps=200):
     info = s.production(0, timed_sweeps)
     s.close()
     return info["attempts"] / (info["kernel_ms"] * 1e-3), info["kernel_ms"] / info["kernel_launches"]
+
+
+KERNEL_SOURCES = ["muca_kernels.hip", "muca_sweep_fast.hip", "muca_sweep_split.hip",
+                  "muca_rowbits.h", "philox.h", "muca_device.h"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_sweep_L32_W16384.txt")
+COPY_BYTES = 256 << 20
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1707_00919_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_per_launch():
+    """HBM bytes per sweep launch of the benchmark shape from the committed
+    counter summary (FETCH_SIZE and WRITE_SIZE, each scaled by what it reads
+    for a plain copy), or None if the kernel sources changed since the
+    counters were taken.  The lattices stay in L2 during a launch, so the
+    count does not grow with the sweeps per launch."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    with open(TRAFFIC_FILE) as f:
+        for line in f:
+            if "=" in line and not line.startswith("#"):
+                k, v = line.split("=", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return float(vals["hbm_bytes_per_launch"])
+
+
+def profile_pass(Solver, wl, ln_g, sweeps=50):
+    """Short run for counter collection: one sweep launch of the benchmark
+    shape at exact weights, then a plain device copy of COPY_BYTES bytes that
+    calibrates FETCH_SIZE / WRITE_SIZE."""
+    import torch
+    s = Solver(wl["L"], wl["walkers"], 12345)
+    s.set_log_weights(np.where(np.isfinite(ln_g), -ln_g, 0.0))
+    info = s.production(0, sweeps)
+    s.close()
+    src = torch.ones(COPY_BYTES // 4, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"profile_pass": True, "attempts": info["attempts"],
+                      "kernel_variant": info["kernel_variant"], "copy_bytes": COPY_BYTES,
+                      "kernel_source_sha256_16": kernel_source_hash()}), flush=True)
 
 
 def cpu_baseline(wl, ln_g, sweeps, warm):
@@ -142,6 +202,8 @@ def main():
     ap.add_argument("--cpu-sweeps", type=int, default=40)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-hardware-rate", action="store_true")
+    ap.add_argument("--profile-pass", action="store_true",
+                    help="short sweep + calibration copy for rocprofv3 counter runs")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the method's walkers and histogram live on a "
@@ -157,6 +219,9 @@ def main():
     torch.cuda.set_device(0)
     wl = WORKLOADS[WORKLOAD]
     ln_g = exact_ln_g(wl["L"])
+    if args.profile_pass:
+        profile_pass(Solver, wl, ln_g)
+        return
 
     for i in range(args.warmup):
         r = solve(Solver, wl, 100000 + i, args.iter_cap)
@@ -177,9 +242,15 @@ def main():
     attempts = sum(r["attempts"] for r in runs)
     kernel_ms = sum(r["kernel_ms"] for r in runs)
     launches = sum(r["launches"] for r in runs)
+    variant_ms = {}
+    for r in runs:
+        for v, ms in r["variant_ms"].items():
+            variant_ms[v] = variant_ms.get(v, 0.0) + ms
+    main_variant = max(variant_ms, key=variant_ms.get)
+    traffic = traffic_per_launch()
     avg_launch_s = kernel_ms * 1e-3 / launches
     attempts_per_launch = attempts / launches
-    achieved = ALU_SLOTS_PER_ATTEMPT * attempts_per_launch / avg_launch_s
+    achieved = ALU_OPS_PER_ATTEMPT * attempts_per_launch / avg_launch_s
     ttc = [r["ttc_s"] for r in runs]
     errs = []
     if ln_g is not None:
@@ -219,11 +290,12 @@ def main():
             "peak": VALU_PEAK_OPS / 1e12,
             "unit": "Tops/s",
             "frac": achieved / VALU_PEAK_OPS,
-            "traffic": None,
-            "kernel": "sweep_kernel<32>",
+            "traffic": traffic,
+            "kernel": KERNEL_NAMES[main_variant] + "<32>",
+            "kernel_time_share": variant_ms[main_variant] / kernel_ms,
             "avg_launch_ms": avg_launch_s * 1e3,
             "launches": launches,
-            "slots_per_attempt": ALU_SLOTS_PER_ATTEMPT,
+            "ops_per_attempt": ALU_OPS_PER_ATTEMPT,
         },
     }
     if not args.no_hardware_rate and ln_g is not None:

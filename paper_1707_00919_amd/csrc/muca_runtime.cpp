@@ -170,9 +170,11 @@ void device_table(uint32_t N, const uint64_t* t5, uint64_t* t4)
 }
 
 // Fast-kernel table: S = T - 1 as uint32 for every move out of bin k, indexed
-// by the count m = 0..4 of anti-aligned neighbours (d = 4 - m).  Moves whose
-// target lies outside 0..N are never proposed (the lattice always matches its
-// energy) and get 0.  Returns false when a move that can be proposed has T = 0:
+// by the count m = 0..4 of anti-aligned neighbours (d = 4 - m).  A move can be
+// proposed only between energies some configuration has: never to a target
+// outside 0..N, and never from or to the forbidden bins 1 and N-1 (no
+// configuration has E = -(2N-4) or 2N-4, Sec. 3).  Those entries are never
+// read and get 0.  Returns false when a move that can be proposed has T = 0:
 // r <= T - 1 cannot express "never", so the generic kernel must run.
 bool fast_table(uint32_t N, const uint64_t* t5, uint32_t* f)
 {
@@ -180,7 +182,7 @@ bool fast_table(uint32_t N, const uint64_t* t5, uint32_t* f)
         for (int m = 0; m < 5; ++m) {
             const long kp = (long)k + 2 - m;
             const uint64_t t = t5[(size_t)k * 5 + (4 - m)];
-            if (kp < 0 || kp > (long)N) {
+            if (kp < 0 || kp > (long)N || k == 1 || k == N - 1 || kp == 1 || kp == (long)N - 1) {
                 f[(size_t)k * 5 + m] = 0u;
                 continue;
             }

@@ -6,13 +6,12 @@
 // acceptance min(1, exp[omega(E') - omega(E)]) as an integer threshold), with
 // the per-attempt work cut to what the method needs:
 //
-//  * Bond words.  At the start of a row the lane forms, for the row's sites,
-//    the mismatch with the row above (already updated) and below (not yet),
-//    and a word nb whose bit i says whether sites i and i+1 of the row differ.
-//    nb is kept current as spins flip (a flip of site x toggles bits x-1 and
-//    x), so the number m of anti-aligned neighbours of site x is a popcount
-//    of two nb bits plus two single-bit extracts.  The flipped sites of the
-//    row are recovered from the change of nb at the end of the row.
+//  * Bond words (muca_rowbits.h).  At the start of a row the lane forms a
+//    word nb whose bit i says whether sites i and i+1 of the row differ, kept
+//    current as spins flip, and per site the count of differing neighbours
+//    above and below as a signed 2-bit field; the number m of anti-aligned
+//    neighbours of a site is then one popcount and one bit-field extract.
+//    The row's flipped sites are recovered from the change of nb at the end.
 //  * One LDS record of 28 bytes per energy bin k: the five thresholds of the
 //    moves out of k, ordered by m, the bin's histogram counter and a pad word
 //    (an odd word stride spreads the gathers of a wave over all LDS banks).
@@ -30,6 +29,7 @@
 
 #include <utility>
 
+#include "muca_rowbits.h"
 #include "philox.h"
 
 namespace muca {
@@ -46,19 +46,6 @@ struct FastShape {
     static constexpr int LDS_BYTES = REC * (N + 1);
 };
 
-template <int L>
-struct FastState {
-    static constexpr int WPR = FastShape<L>::WPR;
-    uint32_t up[WPR];   // row y-1, already updated in this sweep
-    uint32_t cur[WPR];  // row y as it was when the row started
-    uint32_t dn[WPR];   // row y+1, not yet updated
-    uint32_t u[WPR];    // cur ^ up: site differs from the site above
-    uint32_t d[WPR];    // cur ^ dn: site differs from the site below
-    uint32_t nb[WPR];   // bit i: site i differs from site i+1 (cyclic), current
-    uint32_t nb0[WPR];  // nb when the row started
-    uint32_t f0;        // 1 if site 0 of the row flipped
-};
-
 struct FastCtx {
     uint32_t blk0;   // Philox block of the first site of the loop step
     uint32_t c1, c2; // sweep counter words
@@ -71,56 +58,12 @@ __device__ __forceinline__ uint32_t lds_load(const uint8_t* lds, uint32_t byte)
     return *reinterpret_cast<const uint32_t*>(lds + byte);
 }
 
-// Row start: mismatch words and the cyclic neighbour-difference word nb.
-template <int L>
-__device__ __forceinline__ void row_begin(FastState<L>& st)
-{
-    using S = FastShape<L>;
-#pragma unroll
-    for (int w = 0; w < S::WPR; ++w) {
-        st.u[w] = st.cur[w] ^ st.up[w];
-        st.d[w] = st.cur[w] ^ st.dn[w];
-        uint32_t next;  // bit i = site i+1 of the row (cyclic)
-        if (w + 1 < S::WPR)
-            next = (st.cur[w] >> 1) | (st.cur[w + 1] << 31);
-        else
-            next = (st.cur[w] >> 1) | ((st.cur[0] & 1u) << (S::LAST - 1));
-        st.nb[w] = st.cur[w] ^ next;
-        st.nb0[w] = st.nb[w];
-    }
-}
-
-// Row end: the flipped sites F solve F_i ^ F_{i+1} = (nb0 ^ nb)_i with F_0 = f0.
-template <int L>
-__device__ __forceinline__ void row_end(FastState<L>& st)
-{
-    using S = FastShape<L>;
-    uint32_t carry = 0u - st.f0;  // all ones if site 0 flipped
-#pragma unroll
-    for (int w = 0; w < S::WPR; ++w) {
-        uint32_t p = st.nb0[w] ^ st.nb[w];
-        p ^= p << 1;
-        p ^= p << 2;
-        p ^= p << 4;
-        p ^= p << 8;
-        p ^= p << 16;  // inclusive prefix xor within the word
-        uint32_t flips = (p << 1) ^ carry;
-        if (w + 1 == S::WPR && S::LAST < 32)
-            flips &= (1u << S::LAST) - 1u;
-        carry ^= 0u - (p >> 31);
-        st.cur[w] ^= flips;
-    }
-}
-
 template <int L, int P>
-__device__ __forceinline__ void fast_attempt(FastState<L>& st, uint32_t& z, Words4& rcur,
+__device__ __forceinline__ void fast_attempt(RowBits<L>& rb, uint32_t& z, Words4& rcur,
                                              Words4& rnext, const FastCtx& c, uint8_t* lds)
 {
     using S = FastShape<L>;
     constexpr int X = P % L;
-    constexpr int W = X >> 5, B = X & 31;
-    constexpr int XL = (X + L - 1) % L;
-    constexpr int WL = XL >> 5, BL = XL & 31;
     if constexpr ((P & 3) == 0) {
         rcur = rnext;
         if constexpr ((P >> 2) + 1 < S::BLOCKS)
@@ -128,31 +71,26 @@ __device__ __forceinline__ void fast_attempt(FastState<L>& st, uint32_t& z, Word
     }
     const uint32_t r = rcur.w[P & 3];
     // ms = (anti-aligned neighbours) - 2 = -(change of the energy bin)
-    const int vert = (int)((st.u[W] >> B) & 1u) + (int)((st.d[W] >> B) & 1u) - 2;
-    int ms;
-    if constexpr (WL == W)
-        ms = __builtin_popcount(st.nb[W] & ((1u << BL) | (1u << B))) + vert;
-    else
-        ms = __builtin_popcount(st.nb[WL] & (1u << BL)) + __builtin_popcount(st.nb[W] & (1u << B)) +
-             vert;
+    const int ms = bond_count<L, X>(rb.nb, vert_minus_two<L, X>(rb));
     const uint32_t thr = lds_load(lds, z + (uint32_t)(ms * 4));
     const uint32_t target = z - (uint32_t)(ms * 28);
     const bool accept = r <= thr;
     z = accept ? target : z;
-    if constexpr (WL == W) {
-        constexpr uint32_t M = (1u << BL) | (1u << B);
-        st.nb[W] = accept ? (st.nb[W] ^ M) : st.nb[W];
-    } else {
-        st.nb[WL] = accept ? (st.nb[WL] ^ (1u << BL)) : st.nb[WL];
-        st.nb[W] = accept ? (st.nb[W] ^ (1u << B)) : st.nb[W];
-    }
+    uint32_t nbf[S::WPR];
+#pragma unroll
+    for (int w = 0; w < S::WPR; ++w)
+        nbf[w] = rb.nb[w];
+    bond_flip<L, X>(nbf);
+#pragma unroll
+    for (int w = 0; w < S::WPR; ++w)
+        rb.nb[w] = accept ? nbf[w] : rb.nb[w];
     if constexpr (X == 0)
-        st.f0 = accept ? 1u : 0u;
+        rb.f0 = accept ? 1u : 0u;
     atomicAdd(reinterpret_cast<uint32_t*>(lds + z + 12), c.inc);
 }
 
 template <int L, int RR, int... Xs>
-__device__ __forceinline__ void fast_row_sites(FastState<L>& st, uint32_t& z, Words4& rcur,
+__device__ __forceinline__ void fast_row_sites(RowBits<L>& st, uint32_t& z, Words4& rcur,
                                                Words4& rnext, const FastCtx& c, uint8_t* lds,
                                                std::integer_sequence<int, Xs...>)
 {
@@ -160,7 +98,7 @@ __device__ __forceinline__ void fast_row_sites(FastState<L>& st, uint32_t& z, Wo
 }
 
 template <int L, int RR>
-__device__ __forceinline__ void fast_row_step(FastState<L>& st, uint32_t& z, Words4& rcur,
+__device__ __forceinline__ void fast_row_step(RowBits<L>& st, uint32_t& z, Words4& rcur,
                                               Words4& rnext, const FastCtx& c, uint8_t* lds,
                                               uint32_t* mine, size_t stride, int y)
 {
@@ -171,9 +109,9 @@ __device__ __forceinline__ void fast_row_step(FastState<L>& st, uint32_t& z, Wor
 #pragma unroll
     for (int j = 0; j < WPR; ++j)
         nx[j] = mine[(size_t)(ynext * WPR + j) * stride];
-    row_begin<L>(st);
+    rowbits_begin<L>(st);
     fast_row_sites<L, RR>(st, z, rcur, rnext, c, lds, std::make_integer_sequence<int, L>{});
-    row_end<L>(st);
+    rowbits_end<L>(st);
 #pragma unroll
     for (int j = 0; j < WPR; ++j) {
         mine[(size_t)(yy * WPR + j) * stride] = st.cur[j];
@@ -204,7 +142,7 @@ __global__ __launch_bounds__(64) void sweep_fast_kernel(FastSweepArgs a)
 
     uint32_t* const mine = a.spins + w;
     const size_t stride = a.wpad;
-    FastState<L> st;
+    RowBits<L> st;
 #pragma unroll
     for (int j = 0; j < WPR; ++j) {
         st.up[j] = mine[(size_t)((L - 1) * WPR + j) * stride];

@@ -21,11 +21,12 @@
 // Per-bin LDS records are 28 bytes (7 words: the five thresholds S = T - 1 by
 // the number m of anti-aligned neighbours, the histogram counter, one pad
 // word): an odd word stride spreads the gathers of 64 lanes over all banks.
-// The bond-word bookkeeping is that of the fast kernel (muca_sweep_fast.hip).
+// The row bookkeeping (bond words, vertical fields) is in muca_rowbits.h.
 #include "muca_device.h"
 
 #include <utility>
 
+#include "muca_rowbits.h"
 #include "philox.h"
 
 namespace muca {
@@ -47,51 +48,13 @@ struct SplitShape {
 
 template <int L>
 struct ChainState {
-    static constexpr int WPR = SplitShape<L>::WPR;
-    uint32_t up[WPR], cur[WPR], dn[WPR];
-    uint32_t u[WPR], d[WPR];  // row mismatch with the rows above / below
-    uint32_t nb[WPR];         // bit i: sites i and i+1 of the row differ (cyclic)
-    uint32_t nb0[WPR];
-    uint32_t f0;              // site 0 of the row flipped
-    uint32_t z;               // byte address of the record of the current bin + 8
-    int ms;                   // (anti-aligned neighbours of the next site) - 2
-    uint32_t thr_keep;        // threshold S of the next site if the previous site
-    uint32_t thr_flip;        // was kept / flipped (loads may still be in flight)
-    bool prev_flip;           // the previous site flipped
+    RowBits<L> rb;
+    uint32_t z;          // byte address of the record of the current bin + 8
+    int ms;              // (anti-aligned neighbours of the next site) - 2
+    uint32_t thr_keep;   // threshold S of the next site if the previous site
+    uint32_t thr_flip;   // was kept / flipped (loads may still be in flight)
+    bool prev_flip;      // the previous site flipped
 };
-
-template <int L, int X>
-__device__ __forceinline__ int vert_minus_two(const ChainState<L>& st)
-{
-    constexpr int W = X >> 5, B = X & 31;
-    return (int)((st.u[W] >> B) & 1u) + (int)((st.d[W] >> B) & 1u) - 2;
-}
-
-// popcount of the two bond bits of site X (bits X-1 and X, cyclic) + acc
-template <int L, int X>
-__device__ __forceinline__ int bond_count(const uint32_t (&nb)[SplitShape<L>::WPR], int acc)
-{
-    constexpr int XL = (X + L - 1) % L;
-    constexpr int W = X >> 5, B = X & 31, WL = XL >> 5, BL = XL & 31;
-    if constexpr (W == WL)
-        return __builtin_popcount(nb[W] & ((1u << B) | (1u << BL))) + acc;
-    else
-        return __builtin_popcount(nb[W] & (1u << B)) + __builtin_popcount(nb[WL] & (1u << BL)) + acc;
-}
-
-// nb after flipping site X (toggles bond bits X-1 and X)
-template <int L, int X>
-__device__ __forceinline__ void bond_flip(uint32_t (&nb)[SplitShape<L>::WPR])
-{
-    constexpr int XL = (X + L - 1) % L;
-    constexpr int W = X >> 5, B = X & 31, WL = XL >> 5, BL = XL & 31;
-    if constexpr (W == WL) {
-        nb[W] ^= (1u << B) | (1u << BL);
-    } else {
-        nb[W] ^= 1u << B;
-        nb[WL] ^= 1u << BL;
-    }
-}
 
 __device__ __forceinline__ uint32_t lds_u32(const uint8_t* lds, uint32_t byte)
 {
@@ -101,44 +64,11 @@ __device__ __forceinline__ uint32_t lds_u32(const uint8_t* lds, uint32_t byte)
 template <int L>
 __device__ __forceinline__ void chain_row_begin(ChainState<L>& st, const uint8_t* lds)
 {
-    using S = SplitShape<L>;
-#pragma unroll
-    for (int w = 0; w < S::WPR; ++w) {
-        st.u[w] = st.cur[w] ^ st.up[w];
-        st.d[w] = st.cur[w] ^ st.dn[w];
-        uint32_t next;
-        if (w + 1 < S::WPR)
-            next = (st.cur[w] >> 1) | (st.cur[w + 1] << 31);
-        else
-            next = (st.cur[w] >> 1) | ((st.cur[0] & 1u) << (S::LAST - 1));
-        st.nb[w] = st.cur[w] ^ next;
-        st.nb0[w] = st.nb[w];
-    }
-    st.ms = bond_count<L, 0>(st.nb, vert_minus_two<L, 0>(st));
+    rowbits_begin<L>(st.rb);
+    st.ms = bond_count<L, 0>(st.rb.nb, vert_minus_two<L, 0>(st.rb));
     st.thr_keep = lds_u32(lds, st.z + (uint32_t)(st.ms * 4));
     st.thr_flip = st.thr_keep;
     st.prev_flip = false;
-}
-
-template <int L>
-__device__ __forceinline__ void chain_row_end(ChainState<L>& st)
-{
-    using S = SplitShape<L>;
-    uint32_t carry = 0u - st.f0;
-#pragma unroll
-    for (int w = 0; w < S::WPR; ++w) {
-        uint32_t p = st.nb0[w] ^ st.nb[w];
-        p ^= p << 1;
-        p ^= p << 2;
-        p ^= p << 4;
-        p ^= p << 8;
-        p ^= p << 16;
-        uint32_t flips = (p << 1) ^ carry;
-        if (w + 1 == S::WPR && S::LAST < 32)
-            flips &= (1u << S::LAST) - 1u;
-        carry ^= 0u - (p >> 31);
-        st.cur[w] ^= flips;
-    }
 }
 
 // Attempt at site X = P % L; P counts the sites of the loop step.
@@ -168,15 +98,15 @@ __device__ __forceinline__ void chain_attempt(ChainState<L>& st, Words4& rc, Wor
     uint32_t nbf[S::WPR];
 #pragma unroll
     for (int w = 0; w < S::WPR; ++w)
-        nbf[w] = st.nb[w];
+        nbf[w] = st.rb.nb[w];
     bond_flip<L, X>(nbf);
     const uint32_t zf = st.z - (uint32_t)(st.ms * 28);
     int ms_keep = 0, ms_flip = 0;
     uint32_t next_keep = 0u, next_flip = 0u;
     if constexpr (X + 1 < L) {
         // both possible thresholds of site X+1
-        const int v1 = vert_minus_two<L, X + 1>(st);
-        ms_keep = bond_count<L, X + 1>(st.nb, v1);
+        const int v1 = vert_minus_two<L, X + 1>(st.rb);
+        ms_keep = bond_count<L, X + 1>(st.rb.nb, v1);
         ms_flip = bond_count<L, X + 1>(nbf, v1);
         next_keep = lds_u32(lds, st.z + (uint32_t)(ms_keep * 4));
         next_flip = lds_u32(lds, zf + (uint32_t)(ms_flip * 4));
@@ -187,9 +117,9 @@ __device__ __forceinline__ void chain_attempt(ChainState<L>& st, Words4& rc, Wor
     st.z = accept ? zf : st.z;
 #pragma unroll
     for (int w = 0; w < S::WPR; ++w)
-        st.nb[w] = accept ? nbf[w] : st.nb[w];
+        st.rb.nb[w] = accept ? nbf[w] : st.rb.nb[w];
     if constexpr (X == 0)
-        st.f0 = accept ? 1u : 0u;
+        st.rb.f0 = accept ? 1u : 0u;
     atomicAdd(reinterpret_cast<uint32_t*>(lds + st.z + 12), inc);
     if constexpr (X + 1 < L) {
         st.ms = accept ? ms_flip : ms_keep;
@@ -221,13 +151,13 @@ __device__ __forceinline__ void chain_row(ChainState<L>& st, Words4& rc, Words4&
         nx[j] = mine[(size_t)(ynext * WPR + j) * stride];
     chain_row_begin<L>(st, lds);
     chain_row_sites<L, RR>(st, rc, rn, lds, slot, lane, inc, std::make_integer_sequence<int, L>{});
-    chain_row_end<L>(st);
+    rowbits_end<L>(st.rb);
 #pragma unroll
     for (int j = 0; j < WPR; ++j) {
-        mine[(size_t)(yy * WPR + j) * stride] = st.cur[j];
-        st.up[j] = st.cur[j];
-        st.cur[j] = st.dn[j];
-        st.dn[j] = nx[j];
+        mine[(size_t)(yy * WPR + j) * stride] = st.rb.cur[j];
+        st.rb.up[j] = st.rb.cur[j];
+        st.rb.cur[j] = st.rb.dn[j];
+        st.rb.dn[j] = nx[j];
     }
 }
 
@@ -281,11 +211,11 @@ __global__ __launch_bounds__(128) void sweep_split_kernel(FastSweepArgs a)
     if (consumer) {
 #pragma unroll
         for (int j = 0; j < WPR; ++j) {
-            st.up[j] = mine[(size_t)((L - 1) * WPR + j) * stride];
-            st.cur[j] = mine[(size_t)j * stride];
-            st.dn[j] = mine[(size_t)(WPR + j) * stride];
+            st.rb.up[j] = mine[(size_t)((L - 1) * WPR + j) * stride];
+            st.rb.cur[j] = mine[(size_t)j * stride];
+            st.rb.dn[j] = mine[(size_t)(WPR + j) * stride];
         }
-        st.f0 = 0u;
+        st.rb.f0 = 0u;
         st.z = 28u * (uint32_t)((a.energy[w] + 2 * N) >> 2) + 8u;
     }
 

@@ -151,6 +151,26 @@ def test_zero_threshold_falls_back_to_generic_kernel():
     assert_state(s, o)
 
 
+def test_forbidden_bins_do_not_disable_the_fast_kernels():
+    # the forbidden bins keep omega = 0 while their neighbours sink far below:
+    # their thresholds are 0, but no configuration ever has those energies
+    note("forbidden-bin thresholds")
+    L, W, seed = 16, 130, 6
+    N = L * L
+    om = smooth_log_weights(L, 5) - 400.0
+    om[1] = 0.0
+    om[N - 1] = 0.0
+    assert oracle.thresholds(N, om)[1, 4] == 0
+    s = Solver(L, W, seed)
+    o = oracle.OracleMuca(L, W, seed)
+    s.set_log_weights(om)
+    o.set_log_weights(om)
+    si = s.iterate(1, 3)
+    assert si["kernel_variant"] == 2
+    assert_call(si, o.iterate(1, 3), s, o)
+    assert_state(s, o)
+
+
 @pytest.mark.parametrize("cap", [1, 3])
 def test_launch_split_does_not_change_results(cap):
     note("launch split cap=%d" % cap)
