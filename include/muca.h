@@ -63,7 +63,9 @@ typedef enum muca_status {
     MUCA_ERR_DEVICE = 3,        /* a HIP call failed; the instance is poisoned */
     MUCA_ERR_OVERFLOW = 4,      /* a merged histogram bin would pass 2^64     */
     MUCA_ERR_NOT_CONVERGED = 5, /* ln g requested but the lowest bin is empty */
-    MUCA_ERR_STATE = 6          /* the instance was poisoned earlier         */
+    MUCA_ERR_STATE = 6,         /* the instance was poisoned earlier, or a
+                                   batch call came out of order              */
+    MUCA_PENDING = 7            /* muca_batch_query: the round still runs    */
 } muca_status;
 
 #define MUCA_MAX_L 128u
@@ -170,6 +172,155 @@ int muca_last_info(const muca_instance* h, muca_info* out);
 /* Message for the last failure on h (NULL: the last failed muca_create of
  * this thread).  Valid until the next call on h.                            */
 const char* muca_last_error(const muca_instance* h);
+
+/* ------------------------------------------------------------------------
+ * Batched form: many independent instances (any mix of L and walker counts)
+ * swept together so that their walkers fill the device.  The method is the
+ * same per instance (Sec. 2.2: independent walker populations, each with its
+ * own weights and histogram); every instance's results are bit-identical to
+ * running it alone.  One round runs, for every member, either a weight
+ * iteration, a production call or nothing; the members' sweeps are grouped by
+ * (L, kernel form) and each group is one launch whose workgroups each take 64
+ * walkers of one member; the groups run concurrently.
+ * ------------------------------------------------------------------------ */
+typedef struct muca_batch muca_batch;
+
+#define MUCA_BATCH_SKIP 0u
+#define MUCA_BATCH_ITERATE 1u
+#define MUCA_BATCH_PRODUCTION 2u
+
+/* batch flags */
+#define MUCA_BATCH_GRAPH 0x1u     /* capture a round's device work in a HIP graph
+                                     and replay it while the round's shape (which
+                                     members run, their sweep counts and kernel
+                                     forms) is unchanged                        */
+#define MUCA_BATCH_AUTOTUNE 0x2u  /* time the two-wave and one-wave kernel forms
+                                     on the first two rounds and keep the faster
+                                     (results do not depend on the choice)      */
+
+/* Group count live instances.  members[] stay owned by the caller and must
+ * outlive the batch; they are not to be called while a round runs, and all
+ * must have been created on the current device.  hip_stream: as for
+ * muca_create.  On failure *out is NULL and muca_batch_last_error(NULL) tells
+ * why.                                                                      */
+int muca_batch_create(muca_instance* const* members, uint32_t count, void* hip_stream,
+                      uint32_t flags, muca_batch** out);
+
+/* One round.  mode[i] is MUCA_BATCH_SKIP, _ITERATE or _PRODUCTION for member
+ * i; therm[i] and sweeps[i] as in muca_iterate.  infos (may be NULL) receives
+ * count entries; kernel_ms is the device time of the whole round.  Member
+ * errors (e.g. a poisoned member) fail the round before any device work; a
+ * device failure during the round poisons the members that ran in it.
+ * Equivalent to muca_batch_submit followed by muca_batch_finish.            */
+int muca_batch_run(muca_batch* b, const uint32_t* mode, const uint32_t* therm,
+                   const uint32_t* sweeps, muca_info* infos);
+
+/* The two halves of muca_batch_run, so that the host can do other work (or
+ * drive other batches) while a round runs.  submit computes the members'
+ * thresholds and enqueues the round without waiting for it (unless a member
+ * needs more than one launch per round); the arrays are copied.  Until
+ * finish, no other batch call on b is allowed and the members must not be
+ * touched.  query returns MUCA_OK once the round has finished on the device,
+ * MUCA_PENDING while it runs; it never blocks.  finish waits for the round
+ * and applies the host half of every member's call (statistics, Eq. 4).   */
+int muca_batch_submit(muca_batch* b, const uint32_t* mode, const uint32_t* therm,
+                      const uint32_t* sweeps);
+int muca_batch_query(muca_batch* b);
+int muca_batch_finish(muca_batch* b, muca_info* infos);
+
+/* Replace the member list between rounds (same rules as muca_batch_create).
+ * Staging buffers are kept while the new members fit in them, so a batch
+ * whose membership changes often (continuous batching) does not allocate or
+ * free device memory each time.  Autotuner results are kept.                */
+int muca_batch_set_members(muca_batch* b, muca_instance* const* members, uint32_t count);
+
+int muca_batch_destroy(muca_batch* b);
+
+const char* muca_batch_last_error(const muca_batch* b);
+
+/* ------------------------------------------------------------------------
+ * Serving form: a request loop with continuous batching.  A request is one
+ * complete solve (Sec. 2.2): weight iterations of iter_sweeps recorded sweeps
+ * (after iter_therm unrecorded ones) until the iteration's flatness (min H /
+ * mean H over the reachable bins) reaches min_flatness, then prod_therm
+ * unrecorded and prod_sweeps recorded sweeps at the final weights, whose
+ * histogram gives ln g (normalisation 0 of muca_log_dos).  Requests are
+ * admitted in arrival order as soon as their device state (muca_state_bytes)
+ * fits in the server's arena and the walker budget allows; admitted requests
+ * stay resident until done.  Requests of equal L form one lane (a batch on
+ * its own stream); lanes run concurrently and each starts its next round as
+ * soon as its previous round ends.  A production run is cut into slices of
+ * at most iter_sweeps sweeps.  Results are bit-identical to running the
+ * request alone (muca_iterate, muca_production(prod_therm, prod_sweeps),
+ * muca_log_dos).  The server is driven by muca_server_progress, which never
+ * blocks on the device.  Times are seconds since the server was created.
+ * ------------------------------------------------------------------------ */
+typedef struct muca_server muca_server;
+
+typedef struct muca_server_config {
+    uint64_t mem_cap_bytes;       /* device arena for request state (allocated
+                                     once, at creation)                       */
+    uint64_t max_active_walkers;  /* admit while the admitted walkers stay
+                                     within this (0: no limit)               */
+    uint32_t batch_flags;         /* MUCA_BATCH_* for the lanes               */
+    uint32_t reserved;
+} muca_server_config;
+
+typedef struct muca_request {
+    double min_flatness;          /* stop iterating at flatness >= this      */
+    uint32_t L, walkers, seed, flags;  /* as in muca_params                  */
+    uint32_t iter_therm;          /* unrecorded sweeps before each iteration */
+    uint32_t iter_sweeps;         /* recorded sweeps per iteration (>= 1)    */
+    uint32_t max_iterations;      /* 0: no cap; at the cap the production
+                                     still runs and the result's status is
+                                     MUCA_ERR_NOT_CONVERGED                  */
+    uint32_t prod_therm, prod_sweeps;
+    uint32_t reserved;
+} muca_request;
+
+typedef struct muca_result {
+    uint64_t ticket;
+    uint64_t attempts;            /* spin-flip attempts of the whole solve    */
+    double flatness;              /* of the last weight iteration            */
+    double t_submit, t_admit;     /* arrival, admission                      */
+    double t_weights;             /* end of the last weight iteration        */
+    double t_done;                /* ln g available                          */
+    int32_t status;               /* MUCA_OK or the error that ended it      */
+    uint32_t iterations;
+} muca_result;
+
+typedef struct muca_server_counters {
+    uint64_t completed, admitted;
+    uint64_t resident_bytes;      /* arena bytes held by admitted requests    */
+    uint64_t active_walkers;
+    uint64_t attempts;            /* all attempts of finished rounds          */
+    double clock_s;
+    uint32_t queued, active;
+} muca_server_counters;
+
+/* Allocates the arena on the current device.  On failure *out is NULL and
+ * muca_server_last_error(NULL) tells why.                                   */
+int muca_server_create(const muca_server_config* cfg, muca_server** out);
+
+/* Queues a request (copied); *ticket identifies it.                         */
+int muca_server_submit(muca_server* s, const muca_request* q, uint64_t* ticket);
+
+/* Collects finished lane rounds, retires finished requests, admits queued
+ * ones and starts the next round of every idle lane.  *events (may be NULL)
+ * counts rounds collected plus rounds started; 0 means nothing changed.     */
+int muca_server_progress(muca_server* s, uint32_t* events);
+
+/* The result of a finished request, then forgets it.  MUCA_PENDING while the
+ * request is queued or running.  ln_g (may be NULL) receives L*L+1 values
+ * (n must equal that), zeros if the request failed.                         */
+int muca_server_take(muca_server* s, uint64_t ticket, muca_result* res, double* ln_g, size_t n);
+
+int muca_server_stats(const muca_server* s, muca_server_counters* out);
+
+/* Waits for running rounds, then frees everything.                          */
+int muca_server_destroy(muca_server* s);
+
+const char* muca_server_last_error(const muca_server* s);
 
 #ifdef __cplusplus
 }

@@ -64,3 +64,22 @@ def parity_cases():
         (16, 64, 6), (16, 257, 7), (24, 96, 8), (30, 70, 9), (32, 128, 10), (32, 4097, 11),
         (34, 66, 12), (48, 80, 13), (64, 64, 14), (128, 65, 15),
     ]
+
+
+# The batched workload: 48 independent instances of uneven size.  L is drawn
+# uniformly from BATCH_LS, then the walker counts log-uniformly on
+# [256, 8192] (rounded, no alignment), both from default_rng(0); instance i
+# has seed i + 1.  Every instance runs weight iterations of 200 sweeps until
+# its flatness reaches 0.5 (or the iteration cap), then a 2000-sweep
+# production run preceded by 2000 unrecorded sweeps.
+BATCH_LS = (8, 12, 16, 24, 32, 48, 64)
+BATCH_WORKLOAD = dict(instances=48, iter_sweeps=200, min_flat=0.5, max_iterations=400,
+                      prod_sweeps=2000, prod_therm_sweeps=2000)
+
+
+def batch_instances(count=48, rng_seed=0):
+    """[(L, walkers, seed)] of the batched workload."""
+    rng = np.random.default_rng(rng_seed)
+    Ls = rng.choice(np.array(BATCH_LS), size=count)
+    walkers = np.rint(np.exp(rng.uniform(np.log(256.0), np.log(8192.0), size=count))).astype(int)
+    return [(int(L), int(W), i + 1) for i, (L, W) in enumerate(zip(Ls, walkers))]

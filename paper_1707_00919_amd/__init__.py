@@ -8,4 +8,5 @@ the final weights estimates the density of states.  The work runs in
 this package only binds it.
 """
 from ._abi import LIB_PATH, MUCA_MAX_L, lib  # noqa: F401
-from .solver import MucaError, Solver, state_bytes  # noqa: F401
+from .solver import Batch, MucaError, Solver, state_bytes  # noqa: F401
+from .server import Server  # noqa: F401

@@ -16,9 +16,10 @@ MUCA_ERR_DEVICE = 3
 MUCA_ERR_OVERFLOW = 4
 MUCA_ERR_NOT_CONVERGED = 5
 MUCA_ERR_STATE = 6
+MUCA_PENDING = 7
 STATUS_NAMES = {
     0: "MUCA_OK", 1: "MUCA_ERR_INVALID_ARG", 2: "MUCA_ERR_OUT_OF_MEMORY", 3: "MUCA_ERR_DEVICE",
-    4: "MUCA_ERR_OVERFLOW", 5: "MUCA_ERR_NOT_CONVERGED", 6: "MUCA_ERR_STATE",
+    4: "MUCA_ERR_OVERFLOW", 5: "MUCA_ERR_NOT_CONVERGED", 6: "MUCA_ERR_STATE", 7: "MUCA_PENDING",
 }
 MUCA_MAX_L = 128
 MUCA_FLAG_GENERIC_KERNEL = 0x10000
@@ -49,6 +50,41 @@ _U32 = ctypes.c_uint32
 _INT = ctypes.c_int
 
 # name -> (restype, argtypes); every function declared in include/muca.h
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("mem_cap_bytes", ctypes.c_uint64), ("max_active_walkers", ctypes.c_uint64),
+                ("batch_flags", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("min_flatness", ctypes.c_double),
+                ("L", ctypes.c_uint32), ("walkers", ctypes.c_uint32), ("seed", ctypes.c_uint32),
+                ("flags", ctypes.c_uint32), ("iter_therm", ctypes.c_uint32),
+                ("iter_sweeps", ctypes.c_uint32), ("max_iterations", ctypes.c_uint32),
+                ("prod_therm", ctypes.c_uint32), ("prod_sweeps", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("ticket", ctypes.c_uint64), ("attempts", ctypes.c_uint64),
+                ("flatness", ctypes.c_double), ("t_submit", ctypes.c_double),
+                ("t_admit", ctypes.c_double), ("t_weights", ctypes.c_double),
+                ("t_done", ctypes.c_double), ("status", ctypes.c_int32),
+                ("iterations", ctypes.c_uint32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class ServerCounters(ctypes.Structure):
+    _fields_ = [("completed", ctypes.c_uint64), ("admitted", ctypes.c_uint64),
+                ("resident_bytes", ctypes.c_uint64), ("active_walkers", ctypes.c_uint64),
+                ("attempts", ctypes.c_uint64), ("clock_s", ctypes.c_double),
+                ("queued", ctypes.c_uint32), ("active", ctypes.c_uint32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 PROTOTYPES = {
     "muca_state_bytes": (_SZ, [ctypes.POINTER(MucaParams)]),
     "muca_create": (_INT, [ctypes.POINTER(MucaParams), _P, _P, _SZ, ctypes.POINTER(_P)]),
@@ -64,7 +100,28 @@ PROTOTYPES = {
     "muca_log_dos": (_INT, [_P, _INT, _P, _SZ]),
     "muca_last_info": (_INT, [_P, ctypes.POINTER(MucaInfo)]),
     "muca_last_error": (ctypes.c_char_p, [_P]),
+    "muca_batch_create": (_INT, [ctypes.POINTER(_P), _U32, _P, _U32, ctypes.POINTER(_P)]),
+    "muca_batch_run": (_INT, [_P, _P, _P, _P, ctypes.POINTER(MucaInfo)]),
+    "muca_batch_set_members": (_INT, [_P, ctypes.POINTER(_P), _U32]),
+    "muca_batch_submit": (_INT, [_P, _P, _P, _P]),
+    "muca_batch_query": (_INT, [_P]),
+    "muca_batch_finish": (_INT, [_P, ctypes.POINTER(MucaInfo)]),
+    "muca_batch_destroy": (_INT, [_P]),
+    "muca_batch_last_error": (ctypes.c_char_p, [_P]),
+    "muca_server_create": (_INT, [ctypes.POINTER(ServerConfig), ctypes.POINTER(_P)]),
+    "muca_server_submit": (_INT, [_P, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]),
+    "muca_server_progress": (_INT, [_P, ctypes.POINTER(_U32)]),
+    "muca_server_take": (_INT, [_P, ctypes.c_uint64, ctypes.POINTER(Result), _P, ctypes.c_size_t]),
+    "muca_server_stats": (_INT, [_P, ctypes.POINTER(ServerCounters)]),
+    "muca_server_destroy": (_INT, [_P]),
+    "muca_server_last_error": (ctypes.c_char_p, [_P]),
 }
+
+MUCA_BATCH_SKIP = 0
+MUCA_BATCH_ITERATE = 1
+MUCA_BATCH_PRODUCTION = 2
+MUCA_BATCH_GRAPH = 0x1
+MUCA_BATCH_AUTOTUNE = 0x2
 
 _lib = None
 

@@ -20,7 +20,8 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libmuca.so")
 ARCH = "gfx950"
 
-SOURCES = ["muca_kernels.hip", "muca_sweep_fast.hip", "muca_sweep_split.hip", "muca_runtime.cpp"]
+SOURCES = ["muca_kernels.hip", "muca_sweep_fast.hip", "muca_sweep_split.hip", "muca_runtime.cpp",
+           "muca_batch.cpp", "muca_server.cpp"]
 COMMON = [
     "-O3", "-std=c++17", "-fPIC", "-Wall",
     "-ffp-contract=off", "-fno-fast-math",
@@ -39,7 +40,9 @@ def hipcc():
 def _compile(src, obj_dir):
     path = os.path.join(CSRC, src)
     obj = os.path.join(obj_dir, src + ".o")
-    cmd = [hipcc()] + COMMON + (DEVICE if src.endswith(".hip") else []) + ["-c", path, "-o", obj]
+    # host-only sources are still HIP translation units (they include the HIP
+    # runtime); they hold no kernels, but are built for the same target
+    cmd = [hipcc()] + COMMON + DEVICE + ["-c", path, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("hipcc failed for %s:\n%s\n%s" % (src, " ".join(cmd), r.stderr))

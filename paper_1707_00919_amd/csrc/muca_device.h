@@ -54,6 +54,13 @@ struct FastSweepArgs {
     uint32_t pad;
 };
 
+// One workgroup of a batched launch: block `block` (64 walkers) of batch
+// member `member`; the member's arguments are args[member].
+struct BatchItem {
+    uint32_t member;
+    uint32_t block;
+};
+
 struct InitArgs {
     uint32_t* spins;
     int32_t* energy;
@@ -83,5 +90,14 @@ hipError_t launch_split_sweep(uint32_t L, const FastSweepArgs& a, hipStream_t s)
 hipError_t launch_init(const InitArgs& a, hipStream_t s);
 hipError_t launch_sweep(uint32_t L, const SweepArgs& a, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* p, size_t n, hipStream_t s);
+
+// Batched forms: one launch runs nitems workgroups, each described by
+// items[i], all members of the batch having the same L.
+hipError_t launch_sweep_batch(uint32_t L, const SweepArgs* args, const BatchItem* items,
+                              uint32_t nitems, hipStream_t s);
+hipError_t launch_fast_batch(uint32_t L, const FastSweepArgs* args, const BatchItem* items,
+                             uint32_t nitems, hipStream_t s);
+hipError_t launch_split_batch(uint32_t L, const FastSweepArgs* args, const BatchItem* items,
+                              uint32_t nitems, hipStream_t s);
 
 }  // namespace muca

@@ -1,0 +1,76 @@
+// muca_internal.h -- host-side state shared by the instance runtime and the
+// batched runtime of libmuca.  Not part of the public C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "muca.h"
+
+namespace muca_host {
+
+struct Layout {
+    size_t spins_off, spins_bytes;
+    size_t energy_off, energy_bytes;
+    size_t hist_off, hist_bytes;
+    size_t table_off, table_bytes;
+    size_t total;
+};
+
+// Acceptance thresholds T[k*5+d] from the log weights (IEEE double, libm exp).
+void compute_thresholds(uint32_t N, const double* om, uint64_t* t5);
+// Generic-kernel table: uint64 thresholds of the four energy-changing moves.
+void device_table(uint32_t N, const uint64_t* t5, uint64_t* t4);
+// Fast/split-kernel table: uint32 T - 1 by number of anti-aligned neighbours;
+// false if a move that can be proposed has T = 0.
+bool fast_table(uint32_t N, const uint64_t* t5, uint32_t* f);
+double flatness_of(uint32_t N, const uint64_t* H);
+double chebyshev_of(uint32_t N, const uint64_t* H);
+double kl_of(uint32_t N, const uint64_t* H, int width_prev);
+int width_of(uint32_t N, const uint64_t* H);
+
+}  // namespace muca_host
+
+struct muca_instance {
+    muca_params p{};
+    uint32_t L = 0, N = 0, wpr = 0, wpad = 0;
+    int device = 0;
+    int cus = 256;  // compute units of the device
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    void* ws = nullptr;
+    bool own_ws = false;
+    muca_host::Layout lay{};
+    uint32_t* d_spins = nullptr;
+    int32_t* d_energy = nullptr;
+    unsigned long long* d_hist = nullptr;
+    uint64_t* d_table = nullptr;
+    uint64_t* h_table4 = nullptr;  // pinned staging for the device table
+    uint64_t* h_hist = nullptr;    // pinned staging for the histogram
+    hipEvent_t ev_start = nullptr, ev_stop = nullptr;
+    std::vector<double> omega;
+    std::vector<uint64_t> table5;  // thresholds of the last sweep call
+    std::vector<uint64_t> hist;    // histogram of the last recorded call
+    uint64_t sweep_counter = 0;
+    uint32_t iteration = 0;
+    int width_prev = 0;
+    muca_info last{};
+    bool poisoned = false;
+    std::string err;
+};
+
+
+namespace muca_host {
+
+// Apply the results of a finished recorded call (histogram already in
+// h->hist): checks sum H, fills the statistics, applies Eq. 4 when `update`.
+// Returns MUCA_OK or an error code (the instance is then poisoned).
+int finish_call(muca_instance* h, uint32_t therm, uint32_t sweeps, bool update, double kernel_ms,
+                uint32_t launches, uint32_t variant, muca_info* info);
+
+}  // namespace muca_host

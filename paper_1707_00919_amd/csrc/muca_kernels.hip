@@ -109,7 +109,7 @@ __device__ __forceinline__ void row_step(RowWindow<L>& rw, int& k, Words4& r4, c
 }
 
 template <int L>
-__global__ __launch_bounds__(64) void sweep_kernel(SweepArgs a)
+__device__ __forceinline__ void sweep_kernel_body(const SweepArgs& a, uint32_t block)
 {
     using S = Shape<L>;
     constexpr int N = S::N;
@@ -119,7 +119,7 @@ __global__ __launch_bounds__(64) void sweep_kernel(SweepArgs a)
     __shared__ uint32_t lds_hist[N + 1];
 
     const uint32_t lane = threadIdx.x;
-    const uint32_t w = blockIdx.x * kWave + lane;
+    const uint32_t w = block * kWave + lane;
 
     if constexpr (S::kTableInLds) {
         for (int e = lane; e < 4 * (N + 1); e += kWave)
@@ -214,6 +214,26 @@ __global__ __launch_bounds__(256) void fill_u64_kernel(unsigned long long* p, si
 }
 
 template <int L>
+__global__ __launch_bounds__(64) void sweep_kernel(SweepArgs a)
+{
+    sweep_kernel_body<L>(a, blockIdx.x);
+}
+
+template <int L>
+__global__ __launch_bounds__(64) void sweep_kernel_batch(const SweepArgs* args, const BatchItem* items)
+{
+    const BatchItem it = items[blockIdx.x];
+    sweep_kernel_body<L>(args[it.member], it.block);
+}
+
+template <int L>
+hipError_t launch_sweep_L_batch_L(const SweepArgs* args, const BatchItem* items, uint32_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(sweep_kernel_batch<L>, dim3(n), dim3(kWave), 0, s, args, items);
+    return hipGetLastError();
+}
+
+template <int L>
 hipError_t launch_sweep_L(const SweepArgs& a, hipStream_t s)
 {
     hipLaunchKernelGGL(sweep_kernel<L>, dim3(a.wpad / kWave), dim3(kWave), 0, s, a);
@@ -267,6 +287,22 @@ hipError_t launch_fill_u64(unsigned long long* p, size_t n, hipStream_t s)
     hipLaunchKernelGGL(fill_u64_kernel, dim3((unsigned)((n + threads - 1) / threads)),
                        dim3(threads), 0, s, p, n);
     return hipGetLastError();
+}
+
+hipError_t launch_sweep_batch(uint32_t L, const SweepArgs* args, const BatchItem* items, uint32_t nitems,
+                              hipStream_t s)
+{
+    if (nitems == 0)
+        return hipSuccess;
+    switch (L) {
+#define MUCA_CASE(LL) \
+    case LL:          \
+        return launch_sweep_L_batch_L<LL>(args, items, nitems, s);
+        MUCA_FOR_EACH_L(MUCA_CASE)
+#undef MUCA_CASE
+    default:
+        return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace muca

@@ -17,20 +17,13 @@
 #include <vector>
 
 #include "muca_device.h"
+#include "muca_internal.h"
 
 namespace {
 
 constexpr size_t kAlign = 256;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
-
-struct Layout {
-    size_t spins_off, spins_bytes;
-    size_t energy_off, energy_bytes;
-    size_t hist_off, hist_bytes;
-    size_t table_off, table_bytes;
-    size_t total;
-};
 
 bool params_valid(const muca_params* p, std::string* why)
 {
@@ -57,9 +50,9 @@ bool params_valid(const muca_params* p, std::string* why)
     return true;
 }
 
-Layout layout_for(const muca_params* p)
+muca_host::Layout layout_for(const muca_params* p)
 {
-    Layout l{};
+    muca_host::Layout l{};
     const size_t L = p->L, N = L * L;
     const size_t wpad = muca::padded_walkers(p->walkers);
     const size_t words = L * muca::words_per_row(p->L);
@@ -83,34 +76,6 @@ Layout layout_for(const muca_params* p)
 thread_local std::string g_create_error;
 
 }  // namespace
-
-struct muca_instance {
-    muca_params p{};
-    uint32_t L = 0, N = 0, wpr = 0, wpad = 0;
-    int device = 0;
-    int cus = 256;  // compute units of the device
-    hipStream_t stream = nullptr;
-    bool own_stream = false;
-    void* ws = nullptr;
-    bool own_ws = false;
-    Layout lay{};
-    uint32_t* d_spins = nullptr;
-    int32_t* d_energy = nullptr;
-    unsigned long long* d_hist = nullptr;
-    uint64_t* d_table = nullptr;
-    uint64_t* h_table4 = nullptr;  // pinned staging for the device table
-    uint64_t* h_hist = nullptr;    // pinned staging for the histogram
-    hipEvent_t ev_start = nullptr, ev_stop = nullptr;
-    std::vector<double> omega;
-    std::vector<uint64_t> table5;  // thresholds of the last sweep call
-    std::vector<uint64_t> hist;    // histogram of the last recorded call
-    uint64_t sweep_counter = 0;
-    uint32_t iteration = 0;
-    int width_prev = 0;
-    muca_info last{};
-    bool poisoned = false;
-    std::string err;
-};
 
 namespace {
 
@@ -137,6 +102,10 @@ int device_fail(muca_instance* h, hipError_t e, const char* what)
         if (e_ != hipSuccess)                       \
             return device_fail((h), e_, (what));    \
     } while (0)
+
+}  // namespace
+
+namespace muca_host {
 
 // Acceptance thresholds (Sec. 2.3 acceptance min(1, exp[omega(E') - omega(E)])
 // as an integer bound on a uint32 draw): T[k*5+d], k' = k + d - 2.
@@ -194,7 +163,7 @@ bool fast_table(uint32_t N, const uint64_t* t5, uint32_t* f)
     return true;
 }
 
-bool reachable(uint32_t N, uint32_t k) { return k != 1 && k != N - 1; }
+static bool reachable(uint32_t N, uint32_t k) { return k != 1 && k != N - 1; }
 
 double flatness_of(uint32_t N, const uint64_t* H)
 {
@@ -262,6 +231,60 @@ int width_of(uint32_t N, const uint64_t* H)
     }
     return lo < 0 ? 0 : hi - lo + 1;
 }
+
+int finish_call(muca_instance* h, uint32_t therm, uint32_t sweeps, bool update, double kernel_ms,
+                uint32_t launches, uint32_t variant, muca_info* info)
+{
+    const uint32_t N = h->N;
+    const uint64_t total = (uint64_t)therm + sweeps;
+    h->sweep_counter += total;
+    const uint64_t* H = h->hist.data();
+    uint64_t sum = 0;
+    uint32_t visited = 0;
+    for (uint32_t k = 0; k <= N; ++k) {
+        sum += H[k];
+        visited += H[k] > 0;
+    }
+    const uint64_t expect = (uint64_t)h->p.walkers * N * sweeps;
+    if (sum != expect) {
+        h->poisoned = true;
+        char buf[160];
+        std::snprintf(buf, sizeof buf, "histogram sum %llu != walkers*N*sweeps %llu",
+                      (unsigned long long)sum, (unsigned long long)expect);
+        h->err = buf;
+        return MUCA_ERR_DEVICE;
+    }
+    muca_info out{};
+    out.attempts = (uint64_t)h->p.walkers * N * total;
+    out.hist_sum = sum;
+    out.sweep_counter = h->sweep_counter;
+    out.visited_bins = visited;
+    out.flatness = flatness_of(N, H);
+    out.kl_divergence = kl_of(N, H, h->width_prev);
+    out.chebyshev = chebyshev_of(N, H);
+    out.kernel_ms = kernel_ms;
+    out.kernel_launches = launches;
+    out.kernel_variant = variant;
+    h->width_prev = width_of(N, H);
+    if (update) {
+        // Eq. 4, W <- W / H, in logarithmic form; empty bins keep omega.
+        for (uint32_t k = 0; k <= N; ++k)
+            if (H[k] > 0)
+                h->omega[k] -= std::log((double)H[k]);
+        ++h->iteration;
+    }
+    out.iteration = h->iteration;
+    h->last = out;
+    if (info)
+        *info = out;
+    return MUCA_OK;
+}
+
+}  // namespace muca_host
+
+using namespace muca_host;
+
+namespace {
 
 int check_live(const muca_instance* h)
 {
@@ -383,47 +406,8 @@ int run_sweeps(muca_instance* h, uint32_t therm, uint32_t sweeps, bool update, m
     if (launches)
         MUCA_HIP(h, hipEventElapsedTime(&ms, h->ev_start, h->ev_stop), "hipEventElapsedTime");
 
-    h->sweep_counter += total;
     std::memcpy(h->hist.data(), h->h_hist, h->lay.hist_bytes);
-    const uint64_t* H = h->hist.data();
-    uint64_t sum = 0;
-    uint32_t visited = 0;
-    for (uint32_t k = 0; k <= N; ++k) {
-        sum += H[k];
-        visited += H[k] > 0;
-    }
-    const uint64_t expect = (uint64_t)h->p.walkers * N * sweeps;
-    if (sum != expect) {
-        h->poisoned = true;
-        char buf[160];
-        std::snprintf(buf, sizeof buf, "histogram sum %llu != walkers*N*sweeps %llu",
-                      (unsigned long long)sum, (unsigned long long)expect);
-        return fail(h, MUCA_ERR_DEVICE, buf);
-    }
-    muca_info out{};
-    out.attempts = (uint64_t)h->p.walkers * N * total;
-    out.hist_sum = sum;
-    out.sweep_counter = h->sweep_counter;
-    out.visited_bins = visited;
-    out.flatness = flatness_of(N, H);
-    out.kl_divergence = kl_of(N, H, h->width_prev);
-    out.chebyshev = chebyshev_of(N, H);
-    out.kernel_ms = ms;
-    out.kernel_launches = launches;
-    out.kernel_variant = variant;
-    h->width_prev = width_of(N, H);
-    if (update) {
-        // Eq. 4, W <- W / H, in logarithmic form; empty bins keep omega.
-        for (uint32_t k = 0; k <= N; ++k)
-            if (H[k] > 0)
-                h->omega[k] -= std::log((double)H[k]);
-        ++h->iteration;
-    }
-    out.iteration = h->iteration;
-    h->last = out;
-    if (info)
-        *info = out;
-    return MUCA_OK;
+    return finish_call(h, therm, sweeps, update, ms, launches, variant, info);
 }
 
 }  // namespace

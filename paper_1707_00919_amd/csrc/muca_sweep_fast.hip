@@ -122,7 +122,7 @@ __device__ __forceinline__ void fast_row_step(RowBits<L>& st, uint32_t& z, Words
 }
 
 template <int L>
-__global__ __launch_bounds__(64) void sweep_fast_kernel(FastSweepArgs a)
+__device__ __forceinline__ void sweep_fast_kernel_body(const FastSweepArgs& a, uint32_t block)
 {
     using S = FastShape<L>;
     constexpr int N = S::N;
@@ -130,7 +130,7 @@ __global__ __launch_bounds__(64) void sweep_fast_kernel(FastSweepArgs a)
     __shared__ __attribute__((aligned(16))) uint8_t lds[S::LDS_BYTES];
 
     const uint32_t lane = threadIdx.x;
-    const uint32_t w = blockIdx.x * kWave + lane;
+    const uint32_t w = block * kWave + lane;
 
     // records: five thresholds S = T - 1 (by m), a zeroed histogram counter, pad
     uint32_t* rec = reinterpret_cast<uint32_t*>(lds);
@@ -182,6 +182,26 @@ __global__ __launch_bounds__(64) void sweep_fast_kernel(FastSweepArgs a)
 }
 
 template <int L>
+__global__ __launch_bounds__(64) void sweep_fast_kernel(FastSweepArgs a)
+{
+    sweep_fast_kernel_body<L>(a, blockIdx.x);
+}
+
+template <int L>
+__global__ __launch_bounds__(64) void sweep_fast_kernel_batch(const FastSweepArgs* args, const BatchItem* items)
+{
+    const BatchItem it = items[blockIdx.x];
+    sweep_fast_kernel_body<L>(args[it.member], it.block);
+}
+
+template <int L>
+hipError_t launch_fast_L_batch_L(const FastSweepArgs* args, const BatchItem* items, uint32_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(sweep_fast_kernel_batch<L>, dim3(n), dim3(kWave), 0, s, args, items);
+    return hipGetLastError();
+}
+
+template <int L>
 hipError_t launch_fast_L(const FastSweepArgs& a, hipStream_t s)
 {
     hipLaunchKernelGGL(sweep_fast_kernel<L>, dim3(a.wpad / kWave), dim3(kWave), 0, s, a);
@@ -213,6 +233,22 @@ hipError_t launch_fast_sweep(uint32_t L, const FastSweepArgs& a, hipStream_t s)
 #define MUCA_CASE(LL) \
     case LL:          \
         return launch_fast_L<LL>(a, s);
+        MUCA_FAST_L(MUCA_CASE)
+#undef MUCA_CASE
+    default:
+        return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_fast_batch(uint32_t L, const FastSweepArgs* args, const BatchItem* items, uint32_t nitems,
+                             hipStream_t s)
+{
+    if (nitems == 0)
+        return hipSuccess;
+    switch (L) {
+#define MUCA_CASE(LL) \
+    case LL:          \
+        return launch_fast_L_batch_L<LL>(args, items, nitems, s);
         MUCA_FAST_L(MUCA_CASE)
 #undef MUCA_CASE
     default:

@@ -182,7 +182,7 @@ __device__ __forceinline__ void produce_step(uint8_t* lds, uint32_t s, const Fas
 }
 
 template <int L>
-__global__ __launch_bounds__(128) void sweep_split_kernel(FastSweepArgs a)
+__device__ __forceinline__ void sweep_split_kernel_body(const FastSweepArgs& a, uint32_t block)
 {
     using S = SplitShape<L>;
     static_assert(S::LDS_BYTES <= 160 * 1024, "records and ring must fit in LDS");
@@ -192,7 +192,7 @@ __global__ __launch_bounds__(128) void sweep_split_kernel(FastSweepArgs a)
 
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const bool consumer = threadIdx.x < kWave;  // wave 0: chain; wave 1: random numbers
-    const uint32_t w = blockIdx.x * kWave + lane;
+    const uint32_t w = block * kWave + lane;
     const uint32_t steps = a.nsweeps * (uint32_t)S::STEPS;
 
     uint32_t* rec = reinterpret_cast<uint32_t*>(lds);
@@ -248,6 +248,26 @@ __global__ __launch_bounds__(128) void sweep_split_kernel(FastSweepArgs a)
 }
 
 template <int L>
+__global__ __launch_bounds__(128) void sweep_split_kernel(FastSweepArgs a)
+{
+    sweep_split_kernel_body<L>(a, blockIdx.x);
+}
+
+template <int L>
+__global__ __launch_bounds__(128) void sweep_split_kernel_batch(const FastSweepArgs* args, const BatchItem* items)
+{
+    const BatchItem it = items[blockIdx.x];
+    sweep_split_kernel_body<L>(args[it.member], it.block);
+}
+
+template <int L>
+hipError_t launch_split_L_batch_L(const FastSweepArgs* args, const BatchItem* items, uint32_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(sweep_split_kernel_batch<L>, dim3(n), dim3(2 * kWave), 0, s, args, items);
+    return hipGetLastError();
+}
+
+template <int L>
 hipError_t launch_split_L(const FastSweepArgs& a, hipStream_t s)
 {
     hipLaunchKernelGGL(sweep_split_kernel<L>, dim3(a.wpad / kWave), dim3(2 * kWave), 0, s, a);
@@ -281,6 +301,22 @@ hipError_t launch_split_sweep(uint32_t L, const FastSweepArgs& a, hipStream_t s)
 #define MUCA_CASE(LL) \
     case LL:          \
         return launch_split_L<LL>(a, s);
+        MUCA_SPLIT_L(MUCA_CASE)
+#undef MUCA_CASE
+    default:
+        return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_split_batch(uint32_t L, const FastSweepArgs* args, const BatchItem* items, uint32_t nitems,
+                              hipStream_t s)
+{
+    if (nitems == 0)
+        return hipSuccess;
+    switch (L) {
+#define MUCA_CASE(LL) \
+    case LL:          \
+        return launch_split_L_batch_L<LL>(args, items, nitems, s);
         MUCA_SPLIT_L(MUCA_CASE)
 #undef MUCA_CASE
     default:

@@ -136,3 +136,84 @@ class Solver:
         info = _abi.MucaInfo()
         self._check(self._lib.muca_last_info(self._h, ctypes.byref(info)))
         return info.as_dict()
+
+
+class Batch:
+    """Many independent Solvers swept together (the batched form): one round
+    runs a weight iteration, a production call or nothing for every member,
+    with all members' walkers on the device at once.  Each member's results
+    are bit-identical to running it alone.
+
+    flags: ``_abi.MUCA_BATCH_GRAPH`` (replay a captured HIP graph while the
+    round's shape is unchanged), ``_abi.MUCA_BATCH_AUTOTUNE`` (time the two
+    kernel forms on the first rounds and keep the faster).
+    """
+
+    SKIP, ITERATE, PRODUCTION = (_abi.MUCA_BATCH_SKIP, _abi.MUCA_BATCH_ITERATE,
+                                 _abi.MUCA_BATCH_PRODUCTION)
+
+    def __init__(self, solvers, flags=0, use_torch=True):
+        self._lib = _abi.lib()
+        self.members = list(solvers)
+        self._b = ctypes.c_void_p()
+        handles = (ctypes.c_void_p * len(self.members))(*[s._h.value for s in self.members])
+        stream = None
+        if use_torch:
+            import torch
+            stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+        rc = self._lib.muca_batch_create(handles, len(self.members), stream, flags,
+                                         ctypes.byref(self._b))
+        if rc != _abi.MUCA_OK:
+            msg = self._lib.muca_batch_last_error(None)
+            raise MucaError(rc, msg.decode() if msg else "")
+
+    def set_members(self, solvers):
+        """Replace the members between rounds (buffers are reused when they fit)."""
+        members = list(solvers)
+        handles = (ctypes.c_void_p * len(members))(*[s._h.value for s in members])
+        self._check(self._lib.muca_batch_set_members(self._b, handles, len(members)))
+        self.members = members
+
+    def _check(self, rc):
+        if rc != _abi.MUCA_OK:
+            msg = self._lib.muca_batch_last_error(self._b)
+            raise MucaError(rc, msg.decode() if msg else "")
+
+    def submit(self, modes, therm, sweeps):
+        """Enqueue one round without waiting for it."""
+        n = len(self.members)
+        self._mode = np.ascontiguousarray(np.broadcast_to(modes, (n,)), dtype=np.uint32)
+        th = np.ascontiguousarray(np.broadcast_to(therm, (n,)), dtype=np.uint32)
+        sw = np.ascontiguousarray(np.broadcast_to(sweeps, (n,)), dtype=np.uint32)
+        self._check(self._lib.muca_batch_submit(self._b, _ptr(self._mode), _ptr(th), _ptr(sw)))
+
+    def done(self):
+        """True once the submitted round has finished on the device."""
+        rc = self._lib.muca_batch_query(self._b)
+        if rc == _abi.MUCA_PENDING:
+            return False
+        self._check(rc)
+        return True
+
+    def finish(self):
+        """Wait for the submitted round; per-member info dicts (None: skipped)."""
+        n = len(self.members)
+        infos = (_abi.MucaInfo * n)()
+        self._check(self._lib.muca_batch_finish(self._b, infos))
+        return [infos[i].as_dict() if self._mode[i] else None for i in range(n)]
+
+    def run(self, modes, therm, sweeps):
+        """One round: submit, then finish."""
+        self.submit(modes, therm, sweeps)
+        return self.finish()
+
+    def close(self):
+        if self._b:
+            self._lib.muca_batch_destroy(self._b)
+            self._b = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

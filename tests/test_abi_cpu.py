@@ -62,3 +62,32 @@ def test_null_handle_calls_are_rejected(lib):
     assert lib.muca_iterate(None, 0, 1, None) == _abi.MUCA_ERR_INVALID_ARG
     assert lib.muca_histogram(None, None, 0) == _abi.MUCA_ERR_INVALID_ARG
     assert lib.muca_destroy(None) == _abi.MUCA_OK
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """Sizes and field offsets of the ABI structs, as a C compiler lays them
+    out from include/muca.h, equal those of the ctypes mirrors."""
+    import ctypes
+    import subprocess
+    from paper_1707_00919_amd import _abi
+    structs = {"muca_params": _abi.MucaParams, "muca_info": _abi.MucaInfo,
+               "muca_server_config": _abi.ServerConfig, "muca_request": _abi.Request,
+               "muca_result": _abi.Result, "muca_server_counters": _abi.ServerCounters}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "muca.h"', 'int main(void){']
+    for cname, py in structs.items():
+        lines.append('printf("%s size %%zu\\n", sizeof(%s));' % (cname, cname))
+        for f, _ in py._fields_:
+            lines.append('printf("%s %s %%zu\\n", offsetof(%s, %s));' % (cname, f, cname, f))
+    lines.append('return 0;}')
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    inc = os.path.join(ROOT, "include")
+    subprocess.run(["gcc", "-std=c99", "-I", inc, str(src), "-o", str(exe)], check=True)
+    got = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    want = []
+    for cname, py in structs.items():
+        want.append("%s size %d" % (cname, ctypes.sizeof(py)))
+        for f, _ in py._fields_:
+            want.append("%s %s %d" % (cname, f, getattr(py, f).offset))
+    assert [g for g in got if g] == want

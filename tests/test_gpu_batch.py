@@ -1,0 +1,196 @@
+"""The batched form against single-instance runs and the oracle.
+
+A batch sweeps many independent instances (mixed L and walker counts) in
+shared launches; every member's histogram, weights, spins and energies must
+equal, bit for bit, those of the same instance run alone -- with and without
+HIP-graph replay, with the kernel-form autotuner, and when members need more
+than one launch per round.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from muca_inputs import random_log_weights, smooth_log_weights
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [(8, 300, 1), (12, 64, 2), (16, 1000, 3), (24, 130, 4), (32, 700, 5), (48, 100, 6),
+          (62, 70, 7), (64, 128, 8), (96, 65, 9), (6, 65, 10)]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a visible MI355X")
+    yield
+
+
+def note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def bits(a):
+    return np.ascontiguousarray(a, dtype=np.float64).view(np.uint64)
+
+
+def make(shapes, flags=0):
+    from paper_1707_00919_amd import Solver
+    out = []
+    for L, W, seed in shapes:
+        s = Solver(L, W, seed, flags=flags)
+        s.set_log_weights(smooth_log_weights(L, seed))
+        out.append(s)
+    return out
+
+
+def same(a, b):
+    np.testing.assert_array_equal(a.histogram(), b.histogram())
+    np.testing.assert_array_equal(bits(a.log_weights()), bits(b.log_weights()))
+    np.testing.assert_array_equal(a.energies(), b.energies())
+    np.testing.assert_array_equal(a.spins(), b.spins())
+
+
+# rounds: (modes, therm, sweeps) per member
+ROUNDS = [
+    ([1] * 10, [1] * 10, [2] * 10),
+    ([1, 2, 1, 0, 1, 2, 1, 1, 2, 1], [0, 2, 1, 0, 0, 1, 1, 0, 0, 3], [3, 2, 1, 0, 2, 3, 2, 1, 2, 2]),
+    ([2] * 10, [0] * 10, [2] * 10),
+]
+
+
+@pytest.mark.parametrize("flags", [0, 1, 2, 3])
+def test_batch_matches_solo(flags):
+    from paper_1707_00919_amd import Batch
+    note("batch vs solo flags=%d" % flags)
+    solo = make(SHAPES)
+    grouped = make(SHAPES)
+    batch = Batch(grouped, flags=flags)
+    for modes, therm, sweeps in ROUNDS + ROUNDS[:1]:
+        infos = batch.run(modes, therm, sweeps)
+        for i, s in enumerate(solo):
+            if modes[i] == 1:
+                si = s.iterate(therm[i], sweeps[i])
+            elif modes[i] == 2:
+                si = s.production(therm[i], sweeps[i])
+            else:
+                continue
+            assert infos[i]["hist_sum"] == si["hist_sum"]
+            assert infos[i]["flatness"] == si["flatness"]
+            assert infos[i]["sweep_counter"] == si["sweep_counter"]
+    for a, b in zip(solo, grouped):
+        same(a, b)
+    batch.close()
+
+
+def test_batch_matches_oracle_and_splits_launches():
+    # a member capped at 2 sweeps per launch forces several launch chunks
+    from paper_1707_00919_amd import Batch, Solver
+    note("batch vs oracle, chunked")
+    shapes = [(8, 70, 11), (16, 64, 12), (20, 65, 13)]
+    members = [Solver(L, W, s, flags=2 if i == 1 else 0) for i, (L, W, s) in enumerate(shapes)]
+    orcs = [oracle.OracleMuca(L, W, s) for L, W, s in shapes]
+    for (L, W, s), m, o in zip(shapes, members, orcs):
+        om = random_log_weights(L, s, scale=2.0)
+        m.set_log_weights(om)
+        o.set_log_weights(om)
+    batch = Batch(members)
+    infos = batch.run([1, 1, 2], [1, 2, 0], [3, 5, 2])
+    for (m, o, th, sw, md) in zip(members, orcs, [1, 2, 0], [3, 5, 2], [1, 1, 2]):
+        (o.iterate if md == 1 else o.production)(th, sw)
+        np.testing.assert_array_equal(m.histogram(), o.hist)
+        np.testing.assert_array_equal(bits(m.log_weights()), bits(o.omega))
+        np.testing.assert_array_equal(m.energies(), o.energies)
+        np.testing.assert_array_equal(m.spins(), o.spins)
+    assert infos[1]["kernel_launches"] >= 3
+    batch.close()
+
+
+def test_graph_replays_match_eager_rounds():
+    # the same round shape replayed from one captured graph, with eager work
+    # and synchronisations in between, against an eager batch
+    from paper_1707_00919_amd import Batch, _abi
+    note("graph replays")
+    shapes = SHAPES[:5]
+    eager = make(shapes)
+    graphed = make(shapes)
+    be = Batch(eager)
+    bg = Batch(graphed, flags=_abi.MUCA_BATCH_GRAPH)
+    for r in range(4):
+        be.run([1] * 5, [0] * 5, [2] * 5)
+        bg.run([1] * 5, [0] * 5, [2] * 5)
+        for a, b in zip(eager, graphed):
+            np.testing.assert_array_equal(a.histogram(), b.histogram())
+            np.testing.assert_array_equal(bits(a.log_weights()), bits(b.log_weights()))
+    for a, b in zip(eager, graphed):
+        same(a, b)
+
+
+def test_batch_rejects_bad_arguments():
+    from paper_1707_00919_amd import Batch, MucaError, _abi
+    note("batch errors")
+    members = make(SHAPES[:2])
+    with pytest.raises(MucaError) as e:
+        Batch([members[0], members[0]])
+    assert e.value.code == _abi.MUCA_ERR_INVALID_ARG
+    b = Batch(members)
+    with pytest.raises(MucaError) as e:
+        b.run([3, 1], [0, 0], [1, 1])
+    assert e.value.code == _abi.MUCA_ERR_INVALID_ARG
+    b.run([0, 0], [0, 0], [1, 1])   # nothing to do
+
+
+def test_two_batches_in_flight():
+    # two batches submitted back to back run side by side; each member still
+    # matches its solo run, and out-of-order calls are refused
+    import time
+    from paper_1707_00919_amd import Batch, MucaError, _abi
+    note("two batches in flight")
+    shapes_a, shapes_b = SHAPES[:4], SHAPES[4:8]
+    solo = make(shapes_a + shapes_b)
+    ma, mb = make(shapes_a), make(shapes_b)
+    ba, bb = Batch(ma, use_torch=False), Batch(mb, use_torch=False)
+    with pytest.raises(MucaError) as e:
+        ba.finish()
+    assert e.value.code == _abi.MUCA_ERR_STATE
+    for r in range(3):
+        ba.submit([1] * 4, [1] * 4, [3] * 4)
+        bb.submit([2] * 4, [0] * 4, [4] * 4)
+        with pytest.raises(MucaError) as e:
+            ba.submit([1] * 4, [1] * 4, [3] * 4)
+        assert e.value.code == _abi.MUCA_ERR_STATE
+        t0 = time.time()
+        while not (ba.done() and bb.done()):
+            assert time.time() - t0 < 60.0
+            time.sleep(0.001)
+        ia, ib = ba.finish(), bb.finish()
+        assert all(i["sweep_counter"] == 4 * (r + 1) for i in ia + ib)
+        for s in solo[:4]:
+            s.iterate(1, 3)
+        for s in solo[4:]:
+            s.production(0, 4)
+    for a, b in zip(solo, ma + mb):
+        same(a, b)
+
+
+def test_changing_membership():
+    # members join and leave between rounds (continuous batching); buffers are
+    # reused or grown, and every instance still matches its solo run
+    from paper_1707_00919_amd import Batch, _abi
+    note("changing membership")
+    solo = make(SHAPES)
+    pool = make(SHAPES)
+    b = Batch(pool[:2], flags=_abi.MUCA_BATCH_GRAPH)
+    plan = [[0, 1], [0, 1, 2], [2, 3], [3, 4, 5, 6, 7, 8, 9], [0, 9], [5]]
+    for r, idx in enumerate(plan):
+        b.set_members([pool[i] for i in idx])
+        n = len(idx)
+        infos = b.run([1] * n, [r % 2] * n, [2] * n)
+        for k, i in enumerate(idx):
+            si = solo[i].iterate(r % 2, 2)
+            assert infos[k]["sweep_counter"] == si["sweep_counter"]
+    for a, c in zip(solo, pool):
+        same(a, c)

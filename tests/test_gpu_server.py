@@ -1,0 +1,101 @@
+"""The serving form: every request's result is the same alone and in the mix.
+
+Requests of mixed L and walker counts are submitted in two waves to a server
+whose memory cap admits only a few at a time, so requests queue, join running
+lanes and leave them while others run.  Each result (ln g bit for bit, the
+iteration count, the attempts) must equal that of the same solve run alone
+through Solver.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+REQUESTS = [(8, 100, 1), (8, 300, 2), (12, 64, 3), (16, 200, 4), (12, 130, 5), (8, 65, 6),
+            (16, 70, 7), (10, 90, 8)]
+KW = dict(iter_sweeps=20, min_flatness=0.3, max_iterations=40, prod_therm=30, prod_sweeps=50)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a visible MI355X")
+    yield
+
+
+def note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def solo(L, W, seed):
+    from paper_1707_00919_amd import MucaError, Solver
+    s = Solver(L, W, seed, use_torch=False)
+    it = 0
+    flat = False
+    while it < KW["max_iterations"]:
+        info = s.iterate(0, KW["iter_sweeps"])
+        it += 1
+        if info["flatness"] >= KW["min_flatness"]:
+            flat = True
+            break
+    s.production(KW["prod_therm"], KW["prod_sweeps"])
+    try:
+        lng = s.log_dos(0)
+    except MucaError:
+        lng = np.zeros(L * L + 1)
+    s.close()
+    return it, flat, lng
+
+
+@pytest.mark.parametrize("batch_flags", [0, 3])
+def test_served_equals_alone(batch_flags):
+    from paper_1707_00919_amd import Server, state_bytes
+    note("server mix, batch_flags=%d" % batch_flags)
+    cap = sum(sorted(state_bytes(L, W) for L, W, _ in REQUESTS)[-3:]) + 4096
+    srv = Server(cap, batch_flags=batch_flags)
+    tickets = [srv.submit(L, W, s, **KW) for L, W, s in REQUESTS[:5]]
+    max_resident = 0
+    saw_queue = False
+    for _ in range(20):
+        srv.progress()
+        st = srv.stats()
+        max_resident = max(max_resident, st["resident_bytes"])
+        saw_queue |= st["queued"] > 0
+    tickets += [srv.submit(L, W, s, **KW) for L, W, s in REQUESTS[5:]]
+    st = srv.stats()
+    saw_queue |= st["queued"] > 0
+    out = srv.drain(tickets, timeout_s=120.0)
+    st = srv.stats()
+    assert st["completed"] == len(REQUESTS) and st["active"] == 0 and st["queued"] == 0
+    assert st["resident_bytes"] == 0
+    assert saw_queue and max_resident <= cap
+    for t, (L, W, seed) in zip(tickets, REQUESTS):
+        res, lng = out[t]
+        it, flat, ref = solo(L, W, seed)
+        assert res["iterations"] == it
+        assert res["status"] == (0 if flat else 5)
+        assert res["attempts"] == W * L * L * (KW["iter_sweeps"] * it + KW["prod_therm"] + KW["prod_sweeps"])
+        assert res["t_submit"] <= res["t_admit"] <= res["t_weights"] <= res["t_done"]
+        np.testing.assert_array_equal(lng.view(np.uint64), ref.view(np.uint64))
+    srv.close()
+
+
+def test_server_rejects_bad_requests():
+    from paper_1707_00919_amd import MucaError, Server, _abi, state_bytes
+    note("server errors")
+    srv = Server(state_bytes(8, 64) + 4096)
+    with pytest.raises(MucaError) as e:
+        srv.submit(7, 64, 1)
+    assert e.value.code == _abi.MUCA_ERR_INVALID_ARG
+    with pytest.raises(MucaError):
+        srv.submit(8, 64, 1, iter_sweeps=0)
+    big = srv.submit(32, 4096, 1, **KW)      # larger than the whole cap
+    ok = srv.submit(8, 64, 2, **KW)
+    out = srv.drain([big, ok], timeout_s=60.0)
+    assert out[big][0]["status"] == _abi.MUCA_ERR_OUT_OF_MEMORY
+    assert out[ok][0]["status"] in (0, 5)
+    srv.close()
