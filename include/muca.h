@@ -93,19 +93,27 @@ typedef struct muca_params {
 } muca_params;
 
 typedef struct muca_info {
-    uint64_t attempts;      /* spin-flip attempts of the call, all sweeps    */
-    uint64_t hist_sum;      /* sum of the histogram = walkers * sweeps * N   */
-    uint64_t sweep_counter; /* instance sweep counter after the call         */
+    uint64_t attempts;      /* spin-flip attempts of the call, all walkers   */
+    uint64_t hist_sum;      /* sum of the histogram = walkers * recorded
+                               attempts per walker                           */
+    uint64_t sweep_counter; /* whole sweeps per walker after the call
+                               (position / N)                                */
+    uint64_t position;      /* attempts per walker after the call; attempt p
+                               is made at site p mod N of sweep p div N      */
     uint32_t iteration;     /* weight updates applied so far                 */
     uint32_t visited_bins;  /* bins with H > 0                               */
     double flatness;        /* min H / mean H over the N-1 reachable bins    */
     double kl_divergence;   /* Eq. 6 with P = H / sum H, Q = 1/max(w', 10),
-                               w' the width in bins of the range covered by
-                               the previous recorded call (0 at first)       */
+                               w' the number of reachable bins inside the
+                               range covered by the previous recorded call
+                               (0 at first)                                  */
     double chebyshev;       /* Eq. A.1: max |H/m - 1|, m = sum H / (N-1)     */
     double kernel_ms;       /* device time of the sweep launches (HIP events) */
     uint32_t kernel_launches; /* sweep kernel launches of the call           */
     uint32_t kernel_variant;  /* 0: generic, 1: fast, 2: split sweep kernel  */
+    uint32_t width;           /* bins from the lowest to the highest visited
+                                 bin of H, inclusive (full range: N + 1)     */
+    uint32_t reserved;
 } muca_info;
 
 /* Device bytes an instance with these parameters holds (lattices, energies,
@@ -138,6 +146,50 @@ int muca_iterate(muca_instance* h, uint32_t therm_sweeps, uint32_t sweeps, muca_
  * Each call replaces the stored histogram, so a caller can split a run into
  * blocks (the paper uses 100 calls for its jackknife errors).               */
 int muca_production(muca_instance* h, uint32_t therm_sweeps, uint32_t sweeps, muca_info* info);
+
+/* The same two calls with counts in attempted spin flips per walker instead
+ * of sweeps: the chain runs attempts position .. position+therm+attempts-1
+ * in typewriter order and may start and stop inside a sweep (the update
+ * counts of the paper's iteration schedule, Sec. 3 and Eq. 7, are in
+ * attempts).  Batched rounds (muca_batch_*) need the instance at a sweep
+ * boundary.                                                                 */
+int muca_iterate_attempts(muca_instance* h, uint64_t therm_attempts, uint64_t attempts,
+                          muca_info* info);
+int muca_production_attempts(muca_instance* h, uint64_t therm_attempts, uint64_t attempts,
+                             muca_info* info);
+
+/* The paper's weight-iteration schedule (Sec. 3, Eq. 6 and Eq. 7), run to
+ * its stop rule.  Iteration n: w = max(w', w_min), w' the range (in bins,
+ * full range N + 1) the previous recorded call covered; f_therm * w
+ * unrecorded attempts per walker, then floor(x) + 1 recorded ones, where
+ * x = 6 w^z / walkers up to and including the first iteration with w = N + 1
+ * and x grows by the factor `growth` in every later iteration; then Eq. 4.
+ * From that first full-range iteration on, the run stops after the first
+ * iteration whose d_k (muca_info.kl_divergence) is below dk_flat.  The
+ * paper's values: z = 2.25, growth = 1.1, dk_flat = 1e-4, f_therm = 30,
+ * w_min = 10.                                                               */
+typedef struct muca_schedule {
+    double z, growth, dk_flat;
+    uint32_t f_therm, w_min;
+    uint32_t max_iterations;  /* give up after this many (> 0)               */
+    uint32_t reserved;
+} muca_schedule;
+
+typedef struct muca_schedule_step {
+    uint64_t therm_attempts;  /* per walker                                  */
+    uint64_t update_attempts; /* recorded attempts per walker                */
+    double kl_divergence, chebyshev, flatness;
+    double kernel_ms;
+    uint32_t width;           /* w of the iteration                          */
+    uint32_t covered;         /* range its histogram covered                 */
+} muca_schedule_step;
+
+/* Runs the schedule from the instance's current state.  steps (may be NULL
+ * when max_steps is 0) receives the first max_steps iterations;
+ * *iterations the number run.  MUCA_OK when the stop rule was met,
+ * MUCA_ERR_NOT_CONVERGED after max_iterations without it.                   */
+int muca_run_schedule(muca_instance* h, const muca_schedule* schedule, muca_schedule_step* steps,
+                      uint32_t max_steps, uint32_t* iterations);
 
 /* Histogram H[k], k = 0..N, of the most recent recorded call.  n_bins must
  * equal N+1.                                                                */

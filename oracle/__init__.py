@@ -58,6 +58,10 @@ def lib():
                                         i32p, u64p, ctypes.c_uint64, ctypes.c_uint32,
                                         ctypes.c_int, u64p, ctypes.c_int]
         c.oracle_sweeps_ids.restype = None
+        c.oracle_attempts_ids.argtypes = [ctypes.c_int, ctypes.c_int, u32p, ctypes.c_uint32, u8p,
+                                          i32p, u64p, ctypes.c_uint64, ctypes.c_uint64,
+                                          ctypes.c_int, u64p, ctypes.c_int]
+        c.oracle_attempts_ids.restype = None
         c.oracle_reweight.argtypes = [ctypes.c_int, dp, u64p]
         c.oracle_reweight.restype = None
         c.oracle_flatness.argtypes = [ctypes.c_int, u64p]
@@ -68,6 +72,8 @@ def lib():
         c.oracle_kl_divergence.restype = ctypes.c_double
         c.oracle_width.argtypes = [ctypes.c_int, u64p]
         c.oracle_width.restype = ctypes.c_int
+        c.oracle_reachable_width.argtypes = [ctypes.c_int, u64p]
+        c.oracle_reachable_width.restype = ctypes.c_int
         c.oracle_log_dos.argtypes = [ctypes.c_int, u64p, dp, ctypes.c_int, dp]
         c.oracle_log_dos.restype = ctypes.c_int
         _lib = c
@@ -127,9 +133,17 @@ def chebyshev(hist):
     return float(lib().oracle_chebyshev(h.size - 1, _p(h, ctypes.c_uint64)))
 
 
-def kl_divergence(hist, width_prev):
+def kl_divergence(hist, reach_prev):
+    """Eq. 6 with Q = 1/max(reach_prev, 10); reach_prev = reachable bins in
+    the previous recorded histogram's range."""
     h = np.ascontiguousarray(hist, dtype=np.uint64)
-    return float(lib().oracle_kl_divergence(h.size - 1, _p(h, ctypes.c_uint64), width_prev))
+    return float(lib().oracle_kl_divergence(h.size - 1, _p(h, ctypes.c_uint64), reach_prev))
+
+
+def reachable_width(hist):
+    """Reachable bins inside the covered energy range."""
+    h = np.ascontiguousarray(hist, dtype=np.uint64)
+    return int(lib().oracle_reachable_width(h.size - 1, _p(h, ctypes.c_uint64)))
 
 
 def width(hist):
@@ -189,9 +203,10 @@ class OracleMuca:
         self.omega = np.zeros(self.N + 1, dtype=np.float64)
         self.hist = np.zeros(self.N + 1, dtype=np.uint64)
         self.table = thresholds(self.N, self.omega)
-        self.sweep_counter = 0
+        self.position = 0     # attempts made per walker so far
         self.iteration = 0
-        self.width_prev = 0
+        self.width_prev = 0   # covered range of the previous recorded call, in bins
+        self.reach_prev = 0   # reachable bins inside it
 
     def _ids_ptr(self):
         return None if self.ids is None else _p(self.ids, ctypes.c_uint32)
@@ -202,46 +217,62 @@ class OracleMuca:
             raise ValueError("omega must be N+1 finite values")
         self.omega = om.copy()
 
-    def _sweeps(self, nsweeps, record):
+    @property
+    def sweep_counter(self):
+        """Whole sweeps made per walker so far."""
+        return self.position // self.N
+
+    def _attempts(self, count, record):
         h = np.zeros(self.N + 1, dtype=np.uint64)
-        if nsweeps:
+        if count:
             t = np.ascontiguousarray(self.table.reshape(-1))
-            lib().oracle_sweeps_ids(self.L, self.W, self._ids_ptr(), self.seed,
-                                    _p(self.spins, ctypes.c_int8),
-                                    _p(self.energies, ctypes.c_int32), _p(t, ctypes.c_uint64),
-                                    self.sweep_counter, nsweeps, 1 if record else 0,
-                                    _p(h, ctypes.c_uint64), self.nthreads)
-            self.sweep_counter += nsweeps
+            lib().oracle_attempts_ids(self.L, self.W, self._ids_ptr(), self.seed,
+                                      _p(self.spins, ctypes.c_int8),
+                                      _p(self.energies, ctypes.c_int32), _p(t, ctypes.c_uint64),
+                                      self.position, count, 1 if record else 0,
+                                      _p(h, ctypes.c_uint64), self.nthreads)
+            self.position += count
         return h
 
-    def _run(self, therm, sweeps):
+    def _run(self, therm, count):
+        """therm unrecorded then count recorded attempts per walker."""
         self.table = thresholds(self.N, self.omega)
-        self._sweeps(therm, False)
-        self.hist = self._sweeps(sweeps, True)
+        self._attempts(therm, False)
+        self.hist = self._attempts(count, True)
         h = self.hist
         info = {
-            "attempts": self.W * self.N * (therm + sweeps),
+            "attempts": self.W * (therm + count),
             "hist_sum": int(h.sum(dtype=np.uint64)),
             "sweep_counter": self.sweep_counter,
+            "position": self.position,
             "visited_bins": int(np.count_nonzero(h)),
             "flatness": flatness(h),
-            "kl_divergence": kl_divergence(h, self.width_prev),
+            "kl_divergence": kl_divergence(h, self.reach_prev),
             "chebyshev": chebyshev(h),
+            "width": width(h),
         }
         self.width_prev = width(h)
+        self.reach_prev = reachable_width(h)
         return info
 
-    def iterate(self, therm, sweeps):
-        info = self._run(therm, sweeps)
+    def iterate_attempts(self, therm, count):
+        """One weight iteration (Eq. 4) over therm + count attempts per walker."""
+        info = self._run(therm, count)
         self.omega = reweight(self.omega, self.hist)
         self.iteration += 1
         info["iteration"] = self.iteration
         return info
 
-    def production(self, therm, sweeps):
-        info = self._run(therm, sweeps)
+    def production_attempts(self, therm, count):
+        info = self._run(therm, count)
         info["iteration"] = self.iteration
         return info
+
+    def iterate(self, therm, sweeps):
+        return self.iterate_attempts(therm * self.N, sweeps * self.N)
+
+    def production(self, therm, sweeps):
+        return self.production_attempts(therm * self.N, sweeps * self.N)
 
     def log_dos(self, norm=0):
         return log_dos(self.hist, self.omega, norm)

@@ -165,39 +165,41 @@ void oracle_thresholds(int N, const double *omega, uint64_t *table)
 }
 
 /* ---------------------------------------------------------------------- */
-/* Sweeps.  Each walker runs its own chain; with record != 0 the energy     */
-/* bin after every attempt is counted.  hist (N+1 entries) is ADDED to.     */
+/* The chain (Sec. 2.3).  Attempts are numbered per walker from 0: attempt  */
+/* p is made at site i = p mod N of sweep p div N (typewriter order), with  */
+/* the draw of (sweep, site).  A call runs attempts pos0 .. pos0+count-1,   */
+/* so it may start and stop inside a sweep; with record != 0 the energy bin */
+/* after every attempt is counted.  hist (N+1 entries) is ADDED to.         */
 /* ---------------------------------------------------------------------- */
-static void walker_sweeps(int L, uint32_t seed, uint32_t walker, int8_t *s, int32_t *energy,
-                          const uint64_t *table, uint64_t sweep0, uint32_t nsweeps, int record,
-                          uint64_t *hist)
+static void walker_attempts(int L, uint32_t seed, uint32_t walker, int8_t *s, int32_t *energy,
+                            const uint64_t *table, uint64_t pos0, uint64_t count, int record,
+                            uint64_t *hist)
 {
     int N = L * L;
     int32_t e = *energy;
-    for (uint32_t t = 0; t < nsweeps; ++t) {
-        uint64_t sweep = sweep0 + t;
-        for (int i = 0; i < N; ++i) {
-            uint32_t r = oracle_draw(seed, walker, sweep, (uint32_t)i, 0);
-            int x = i % L, y = i / L;
-            int nb = s[site_index(L, x - 1, y)] + s[site_index(L, x + 1, y)] +
-                     s[site_index(L, x, y - 1)] + s[site_index(L, x, y + 1)];
-            int de = 2 * s[i] * nb;
-            int d = de / 4 + 2;
-            int k = (e + 2 * N) / 4;
-            if ((uint64_t)r < table[k * 5 + d]) {
-                s[i] = (int8_t)(-s[i]);
-                e += de;
-            }
-            if (record)
-                hist[(e + 2 * N) / 4] += 1;
+    for (uint64_t p = pos0; p < pos0 + count; ++p) {
+        uint64_t sweep = p / (uint64_t)N;
+        int i = (int)(p % (uint64_t)N);
+        uint32_t r = oracle_draw(seed, walker, sweep, (uint32_t)i, 0);
+        int x = i % L, y = i / L;
+        int nb = s[site_index(L, x - 1, y)] + s[site_index(L, x + 1, y)] +
+                 s[site_index(L, x, y - 1)] + s[site_index(L, x, y + 1)];
+        int de = 2 * s[i] * nb;
+        int d = de / 4 + 2;
+        int k = (e + 2 * N) / 4;
+        if ((uint64_t)r < table[k * 5 + d]) {
+            s[i] = (int8_t)(-s[i]);
+            e += de;
         }
+        if (record)
+            hist[(e + 2 * N) / 4] += 1;
     }
     *energy = e;
 }
 
-void oracle_sweeps_ids(int L, int n, const uint32_t *ids, uint32_t seed, int8_t *spins,
-                       int32_t *energies, const uint64_t *table, uint64_t sweep0,
-                       uint32_t nsweeps, int record, uint64_t *hist, int nthreads)
+void oracle_attempts_ids(int L, int n, const uint32_t *ids, uint32_t seed, int8_t *spins,
+                         int32_t *energies, const uint64_t *table, uint64_t pos0, uint64_t count,
+                         int record, uint64_t *hist, int nthreads)
 {
     int N = L * L;
     int nt = 1;
@@ -214,13 +216,23 @@ void oracle_sweeps_ids(int L, int n, const uint32_t *ids, uint32_t seed, int8_t 
         tid = omp_get_thread_num();
 #endif
         uint32_t w = ids ? ids[j] : (uint32_t)j;
-        walker_sweeps(L, seed, w, spins + (size_t)j * N, energies + j, table, sweep0, nsweeps,
-                      record, partial + (size_t)tid * (N + 1));
+        walker_attempts(L, seed, w, spins + (size_t)j * N, energies + j, table, pos0, count,
+                        record, partial + (size_t)tid * (N + 1));
     }
     for (int t = 0; t < nt; ++t)
         for (int k = 0; k <= N; ++k)
             hist[k] += partial[(size_t)t * (N + 1) + k];
     free(partial);
+}
+
+/* Whole sweeps sweep0 .. sweep0+nsweeps-1. */
+void oracle_sweeps_ids(int L, int n, const uint32_t *ids, uint32_t seed, int8_t *spins,
+                       int32_t *energies, const uint64_t *table, uint64_t sweep0,
+                       uint32_t nsweeps, int record, uint64_t *hist, int nthreads)
+{
+    uint64_t N = (uint64_t)L * L;
+    oracle_attempts_ids(L, n, ids, seed, spins, energies, table, sweep0 * N, nsweeps * N, record,
+                        hist, nthreads);
 }
 
 void oracle_sweeps(int L, int W, uint32_t seed, int8_t *spins, int32_t *energies,
@@ -283,15 +295,19 @@ double oracle_chebyshev(int N, const uint64_t *hist)
 }
 
 /* Kullback-Leibler divergence (Sec. 3, Eq. 6) of P = H / sum H from the
- * flat Q = 1/w, w = max(width_prev, 10); empty bins contribute nothing. */
-double oracle_kl_divergence(int N, const uint64_t *hist, int width_prev)
+ * flat Q = 1/w, w = max(w_prev, 10), with w_prev the number of reachable bins
+ * inside the energy range the previous histogram covered (0 at first).  The
+ * paper counts L^2 - 1 accessible energies; Q over reachable bins makes a
+ * flat histogram on the full range give d_k = 0.  Empty bins contribute
+ * nothing. */
+double oracle_kl_divergence(int N, const uint64_t *hist, int w_prev)
 {
     uint64_t sum = 0;
     for (int k = 0; k <= N; ++k)
         sum += hist[k];
     if (sum == 0)
         return 0.0;
-    double w = (double)(width_prev > 10 ? width_prev : 10);
+    double w = (double)(w_prev > 10 ? w_prev : 10);
     double dk = 0.0;
     for (int k = 0; k <= N; ++k) {
         if (hist[k] == 0)
@@ -302,7 +318,8 @@ double oracle_kl_divergence(int N, const uint64_t *hist, int width_prev)
     return dk;
 }
 
-/* Width, in bins, of the energy range a histogram covers. */
+/* Width, in bins, of the energy range a histogram covers (lowest to highest
+ * visited bin, inclusive; the full range is N + 1). */
 int oracle_width(int N, const uint64_t *hist)
 {
     int lo = -1, hi = -1;
@@ -314,6 +331,25 @@ int oracle_width(int N, const uint64_t *hist)
         }
     }
     return lo < 0 ? 0 : hi - lo + 1;
+}
+
+/* Reachable bins inside that range (the forbidden bins 1 and N-1 left out). */
+int oracle_reachable_width(int N, const uint64_t *hist)
+{
+    int lo = -1, hi = -1;
+    for (int k = 0; k <= N; ++k) {
+        if (hist[k] > 0) {
+            if (lo < 0)
+                lo = k;
+            hi = k;
+        }
+    }
+    if (lo < 0)
+        return 0;
+    int n = 0;
+    for (int k = lo; k <= hi; ++k)
+        n += reachable(N, k);
+    return n;
 }
 
 /* ---------------------------------------------------------------------- */

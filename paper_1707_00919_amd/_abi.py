@@ -34,11 +34,13 @@ class MucaParams(ctypes.Structure):
 
 class MucaInfo(ctypes.Structure):
     _fields_ = [("attempts", ctypes.c_uint64), ("hist_sum", ctypes.c_uint64),
-                ("sweep_counter", ctypes.c_uint64), ("iteration", ctypes.c_uint32),
+                ("sweep_counter", ctypes.c_uint64), ("position", ctypes.c_uint64),
+                ("iteration", ctypes.c_uint32),
                 ("visited_bins", ctypes.c_uint32), ("flatness", ctypes.c_double),
                 ("kl_divergence", ctypes.c_double), ("chebyshev", ctypes.c_double),
                 ("kernel_ms", ctypes.c_double), ("kernel_launches", ctypes.c_uint32),
-                ("kernel_variant", ctypes.c_uint32)]
+                ("kernel_variant", ctypes.c_uint32), ("width", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -49,7 +51,22 @@ _SZ = ctypes.c_size_t
 _U32 = ctypes.c_uint32
 _INT = ctypes.c_int
 
-# name -> (restype, argtypes); every function declared in include/muca.h
+class Schedule(ctypes.Structure):
+    _fields_ = [("z", ctypes.c_double), ("growth", ctypes.c_double), ("dk_flat", ctypes.c_double),
+                ("f_therm", ctypes.c_uint32), ("w_min", ctypes.c_uint32),
+                ("max_iterations", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+class ScheduleStep(ctypes.Structure):
+    _fields_ = [("therm_attempts", ctypes.c_uint64), ("update_attempts", ctypes.c_uint64),
+                ("kl_divergence", ctypes.c_double), ("chebyshev", ctypes.c_double),
+                ("flatness", ctypes.c_double), ("kernel_ms", ctypes.c_double),
+                ("width", ctypes.c_uint32), ("covered", ctypes.c_uint32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class ServerConfig(ctypes.Structure):
     _fields_ = [("mem_cap_bytes", ctypes.c_uint64), ("max_active_walkers", ctypes.c_uint64),
                 ("batch_flags", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
@@ -85,6 +102,7 @@ class ServerCounters(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+# name -> (restype, argtypes); every function declared in include/muca.h
 PROTOTYPES = {
     "muca_state_bytes": (_SZ, [ctypes.POINTER(MucaParams)]),
     "muca_create": (_INT, [ctypes.POINTER(MucaParams), _P, _P, _SZ, ctypes.POINTER(_P)]),
@@ -100,6 +118,11 @@ PROTOTYPES = {
     "muca_log_dos": (_INT, [_P, _INT, _P, _SZ]),
     "muca_last_info": (_INT, [_P, ctypes.POINTER(MucaInfo)]),
     "muca_last_error": (ctypes.c_char_p, [_P]),
+    "muca_iterate_attempts": (_INT, [_P, ctypes.c_uint64, ctypes.c_uint64, ctypes.POINTER(MucaInfo)]),
+    "muca_production_attempts": (_INT, [_P, ctypes.c_uint64, ctypes.c_uint64,
+                                        ctypes.POINTER(MucaInfo)]),
+    "muca_run_schedule": (_INT, [_P, ctypes.POINTER(Schedule), ctypes.POINTER(ScheduleStep), _U32,
+                                 ctypes.POINTER(_U32)]),
     "muca_batch_create": (_INT, [ctypes.POINTER(_P), _U32, _P, _U32, ctypes.POINTER(_P)]),
     "muca_batch_run": (_INT, [_P, _P, _P, _P, ctypes.POINTER(MucaInfo)]),
     "muca_batch_set_members": (_INT, [_P, ctypes.POINTER(_P), _U32]),

@@ -384,9 +384,12 @@ int muca_batch_submit(muca_batch* b, const uint32_t* mode, const uint32_t* therm
         const muca_instance* h = b->m[i];
         if (h->poisoned)
             return bfail(b, MUCA_ERR_STATE, "member " + std::to_string(i) + " is poisoned");
-        const uint64_t tot = (uint64_t)therm[i] + sweeps[i];
-        const long double att = (long double)h->p.walkers * h->N * (long double)tot;
-        if (att >= 18446744073709551615.0L || h->sweep_counter + tot < h->sweep_counter)
+        if (h->position % h->N != 0)
+            return bfail(b, MUCA_ERR_INVALID_ARG,
+                         "member " + std::to_string(i) + " stopped inside a sweep; batched rounds run whole sweeps");
+        const uint64_t tot = ((uint64_t)therm[i] + sweeps[i]) * h->N;
+        const long double att = (long double)h->p.walkers * (long double)tot;
+        if (att >= 18446744073709551615.0L || h->position + tot < h->position)
             return bfail(b, MUCA_ERR_OVERFLOW, "member " + std::to_string(i) + " would overflow");
     }
     char* hs = static_cast<char*>(b->h_stage);
@@ -510,10 +513,10 @@ int muca_batch_submit(muca_batch* b, const uint32_t* mode, const uint32_t* therm
             const uint32_t th = s0 >= therm[i] ? 0u : (uint32_t)std::min<uint64_t>(therm[i] - s0, n);
             const char* dtab = static_cast<char*>(b->d_stage) + b->off_tables + b->table_off[i];
             fargs[i] = muca::FastSweepArgs{h->d_spins, h->d_energy, reinterpret_cast<const uint32_t*>(dtab),
-                                           b->d_hist + b->hist_off[i], h->sweep_counter + s0, h->wpad,
+                                           b->d_hist + b->hist_off[i], h->position / h->N + s0, h->wpad,
                                            h->p.walkers, h->p.seed, n, th, 0u};
             gargs[i] = muca::SweepArgs{h->d_spins, h->d_energy, reinterpret_cast<const uint64_t*>(dtab),
-                                       b->d_hist + b->hist_off[i], h->sweep_counter + s0, h->wpad,
+                                       b->d_hist + b->hist_off[i], h->position / h->N + s0, h->wpad,
                                        h->p.walkers, h->p.seed, n, th, 0u};
         }
         const bool single = chunk >= longest;
@@ -599,7 +602,8 @@ int muca_batch_finish(muca_batch* b, muca_info* infos)
             continue;
         muca_instance* h = b->m[i];
         std::memcpy(h->hist.data(), b->h_hist + b->hist_off[i], ((size_t)h->N + 1) * sizeof(uint64_t));
-        const int rc = finish_call(h, b->therm[i], b->sweeps[i], b->mode[i] == MUCA_BATCH_ITERATE, ms,
+        const int rc = finish_call(h, (uint64_t)b->therm[i] * h->N, (uint64_t)b->sweeps[i] * h->N,
+                                   b->mode[i] == MUCA_BATCH_ITERATE, ms,
                                    b->launches, b->form[i], infos ? &infos[i] : nullptr);
         if (rc != MUCA_OK && result == MUCA_OK) {
             result = rc;

@@ -91,6 +91,22 @@ hipError_t launch_init(const InitArgs& a, hipStream_t s);
 hipError_t launch_sweep(uint32_t L, const SweepArgs& a, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* p, size_t n, hipStream_t s);
 
+// Arguments of a partial sweep: sites [site_begin, site_end) of one sweep, in
+// typewriter order, the sites from rec_begin on counted in the histogram.
+// table is in the generic layout (uint64, 4 per bin) or, with fast_table set,
+// in the fast layout (uint32 S = T - 1, 5 per bin).
+struct RangeArgs {
+    uint32_t* spins;
+    int32_t* energy;
+    const void* table;
+    unsigned long long* hist;
+    uint64_t sweep;
+    uint32_t L, wpad, walkers, seed;
+    uint32_t site_begin, site_end, rec_begin;
+    uint32_t fast_table;
+};
+hipError_t launch_sweep_range(const RangeArgs& a, hipStream_t s);
+
 // Batched forms: one launch runs nitems workgroups, each described by
 // items[i], all members of the batch having the same L.
 hipError_t launch_sweep_batch(uint32_t L, const SweepArgs* args, const BatchItem* items,

@@ -31,7 +31,10 @@ void device_table(uint32_t N, const uint64_t* t5, uint64_t* t4);
 bool fast_table(uint32_t N, const uint64_t* t5, uint32_t* f);
 double flatness_of(uint32_t N, const uint64_t* H);
 double chebyshev_of(uint32_t N, const uint64_t* H);
-double kl_of(uint32_t N, const uint64_t* H, int width_prev);
+// Eq. 6 with Q uniform over max(reach_prev, 10) bins.
+double kl_of(uint32_t N, const uint64_t* H, int reach_prev);
+// Reachable bins (not 1 or N-1) between the lowest and highest visited bin.
+int reach_of(uint32_t N, const uint64_t* H);
 int width_of(uint32_t N, const uint64_t* H);
 
 }  // namespace muca_host
@@ -56,9 +59,10 @@ struct muca_instance {
     std::vector<double> omega;
     std::vector<uint64_t> table5;  // thresholds of the last sweep call
     std::vector<uint64_t> hist;    // histogram of the last recorded call
-    uint64_t sweep_counter = 0;
+    uint64_t position = 0;  // attempts made per walker so far (sweep = position / N)
     uint32_t iteration = 0;
-    int width_prev = 0;
+    int width_prev = 0;  // covered range of the last recorded call, in bins
+    int reach_prev = 0;  // reachable bins inside it
     muca_info last{};
     bool poisoned = false;
     std::string err;
@@ -70,7 +74,7 @@ namespace muca_host {
 // Apply the results of a finished recorded call (histogram already in
 // h->hist): checks sum H, fills the statistics, applies Eq. 4 when `update`.
 // Returns MUCA_OK or an error code (the instance is then poisoned).
-int finish_call(muca_instance* h, uint32_t therm, uint32_t sweeps, bool update, double kernel_ms,
+int finish_call(muca_instance* h, uint64_t therm, uint64_t recorded, bool update, double kernel_ms,
                 uint32_t launches, uint32_t variant, muca_info* info);
 
 }  // namespace muca_host

@@ -213,6 +213,61 @@ __global__ __launch_bounds__(256) void fill_u64_kernel(unsigned long long* p, si
         p[i] = 0ull;
 }
 
+// Part of one sweep: the attempts at sites site_begin .. site_end-1 (site i
+// at x = i mod L, y = i div L), for calls that start or stop inside a sweep.
+// A plain lane-per-walker loop on the lattice in memory: it runs at most one
+// sweep per call, next to whole-sweep launches of the kernels above.
+template <bool kFast>
+__global__ __launch_bounds__(64) void sweep_range_kernel(RangeArgs a)
+{
+    extern __shared__ uint32_t range_hist[];
+    const uint32_t L = a.L, N = L * L, wpr = (L + 31u) / 32u;
+    const uint32_t lane = threadIdx.x;
+    const uint32_t w = blockIdx.x * kWave + lane;
+    for (uint32_t b = lane; b <= N; b += kWave)
+        range_hist[b] = 0u;
+    __syncthreads();
+    uint32_t* const mine = a.spins + w;
+    const size_t stride = a.wpad;
+    const uint32_t live = w < a.walkers ? 1u : 0u;
+    const uint32_t c1 = (uint32_t)a.sweep, c2 = (uint32_t)(a.sweep >> 32);
+    int k = (a.energy[w] + 2 * (int)N) >> 2;
+    for (uint32_t i = a.site_begin; i < a.site_end; ++i) {
+        const uint32_t x = i % L, y = i / L;
+        const uint32_t xl = x == 0 ? L - 1 : x - 1, xr = x + 1 == L ? 0 : x + 1;
+        const uint32_t yu = y == 0 ? L - 1 : y - 1, yd = y + 1 == L ? 0 : y + 1;
+        uint32_t* const word = mine + (size_t)(y * wpr + x / 32u) * stride;
+        const uint32_t cur = *word;
+        const uint32_t s = (cur >> (x % 32u)) & 1u;
+        const uint32_t sl = (mine[(size_t)(y * wpr + xl / 32u) * stride] >> (xl % 32u)) & 1u;
+        const uint32_t sr = (mine[(size_t)(y * wpr + xr / 32u) * stride] >> (xr % 32u)) & 1u;
+        const uint32_t su = (mine[(size_t)(yu * wpr + x / 32u) * stride] >> (x % 32u)) & 1u;
+        const uint32_t sd = (mine[(size_t)(yd * wpr + x / 32u) * stride] >> (x % 32u)) & 1u;
+        const uint32_t m = (s ^ sl) + (s ^ sr) + (s ^ su) + (s ^ sd);
+        const uint32_t r = philox10(i >> 2, c1, c2, 0u, a.seed, w).w[i & 3u];
+        bool accept;
+        if constexpr (kFast) {
+            accept = r <= static_cast<const uint32_t*>(a.table)[k * 5 + (int)m];
+        } else {
+            const uint32_t slot = m - (m > 2u ? 1u : 0u);
+            accept = (m == 2u) || ((uint64_t)r < static_cast<const uint64_t*>(a.table)[k * 4 + (int)slot]);
+        }
+        if (accept) {
+            *word = cur ^ (1u << (x % 32u));
+            k += 2 - (int)m;
+        }
+        if (i >= a.rec_begin)
+            atomicAdd(&range_hist[k], live);
+    }
+    a.energy[w] = 4 * k - 2 * (int)N;
+    __syncthreads();
+    for (uint32_t b = lane; b <= N; b += kWave) {
+        const uint32_t v = range_hist[b];
+        if (v)
+            atomicAdd(a.hist + b, (unsigned long long)v);
+    }
+}
+
 template <int L>
 __global__ __launch_bounds__(64) void sweep_kernel(SweepArgs a)
 {
@@ -286,6 +341,31 @@ hipError_t launch_fill_u64(unsigned long long* p, size_t n, hipStream_t s)
     const uint32_t threads = 256;
     hipLaunchKernelGGL(fill_u64_kernel, dim3((unsigned)((n + threads - 1) / threads)),
                        dim3(threads), 0, s, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_sweep_range(const RangeArgs& a, hipStream_t s)
+{
+    if (a.site_begin >= a.site_end)
+        return hipSuccess;
+    if (a.L < 4 || a.L > 128 || a.site_end > a.L * a.L || a.wpad % kWave != 0)
+        return hipErrorInvalidValue;
+    // one 32-bit counter per bin: up to 64 KiB + 4 B at L = 128
+    const size_t lds = ((size_t)a.L * a.L + 1) * sizeof(uint32_t);
+    constexpr int kMaxLds = 128 * 128 * 4 + 4;
+    if (a.fast_table) {
+        static const hipError_t attr = hipFuncSetAttribute(
+            reinterpret_cast<const void*>(&sweep_range_kernel<true>), hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
+        if (attr != hipSuccess)
+            return attr;
+        hipLaunchKernelGGL(sweep_range_kernel<true>, dim3(a.wpad / kWave), dim3(kWave), lds, s, a);
+    } else {
+        static const hipError_t attr = hipFuncSetAttribute(
+            reinterpret_cast<const void*>(&sweep_range_kernel<false>), hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
+        if (attr != hipSuccess)
+            return attr;
+        hipLaunchKernelGGL(sweep_range_kernel<false>, dim3(a.wpad / kWave), dim3(kWave), lds, s, a);
+    }
     return hipGetLastError();
 }
 

@@ -8,6 +8,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -201,14 +202,14 @@ double chebyshev_of(uint32_t N, const uint64_t* H)
     return worst;
 }
 
-double kl_of(uint32_t N, const uint64_t* H, int width_prev)
+double kl_of(uint32_t N, const uint64_t* H, int reach_prev)
 {
     uint64_t sum = 0;
     for (uint32_t k = 0; k <= N; ++k)
         sum += H[k];
     if (sum == 0)
         return 0.0;
-    const double w = (double)(width_prev > 10 ? width_prev : 10);
+    const double w = (double)(reach_prev > 10 ? reach_prev : 10);
     double dk = 0.0;
     for (uint32_t k = 0; k <= N; ++k) {
         if (H[k] == 0)
@@ -217,6 +218,21 @@ double kl_of(uint32_t N, const uint64_t* H, int width_prev)
         dk += p * std::log(p * w);
     }
     return dk;
+}
+
+int reach_of(uint32_t N, const uint64_t* H)
+{
+    int lo = -1, hi = -1;
+    for (uint32_t k = 0; k <= N; ++k)
+        if (H[k] > 0) {
+            if (lo < 0)
+                lo = (int)k;
+            hi = (int)k;
+        }
+    int n = 0;
+    for (int k = lo; lo >= 0 && k <= hi; ++k)
+        n += (k != 1 && k != (int)N - 1) ? 1 : 0;
+    return n;
 }
 
 int width_of(uint32_t N, const uint64_t* H)
@@ -232,12 +248,12 @@ int width_of(uint32_t N, const uint64_t* H)
     return lo < 0 ? 0 : hi - lo + 1;
 }
 
-int finish_call(muca_instance* h, uint32_t therm, uint32_t sweeps, bool update, double kernel_ms,
+int finish_call(muca_instance* h, uint64_t therm, uint64_t recorded, bool update, double kernel_ms,
                 uint32_t launches, uint32_t variant, muca_info* info)
 {
     const uint32_t N = h->N;
-    const uint64_t total = (uint64_t)therm + sweeps;
-    h->sweep_counter += total;
+    const uint64_t total = therm + recorded;
+    h->position += total;
     const uint64_t* H = h->hist.data();
     uint64_t sum = 0;
     uint32_t visited = 0;
@@ -245,27 +261,30 @@ int finish_call(muca_instance* h, uint32_t therm, uint32_t sweeps, bool update, 
         sum += H[k];
         visited += H[k] > 0;
     }
-    const uint64_t expect = (uint64_t)h->p.walkers * N * sweeps;
+    const uint64_t expect = (uint64_t)h->p.walkers * recorded;
     if (sum != expect) {
         h->poisoned = true;
         char buf[160];
-        std::snprintf(buf, sizeof buf, "histogram sum %llu != walkers*N*sweeps %llu",
+        std::snprintf(buf, sizeof buf, "histogram sum %llu != walkers*recorded attempts %llu",
                       (unsigned long long)sum, (unsigned long long)expect);
         h->err = buf;
         return MUCA_ERR_DEVICE;
     }
     muca_info out{};
-    out.attempts = (uint64_t)h->p.walkers * N * total;
+    out.attempts = (uint64_t)h->p.walkers * total;
     out.hist_sum = sum;
-    out.sweep_counter = h->sweep_counter;
+    out.sweep_counter = h->position / N;
+    out.position = h->position;
     out.visited_bins = visited;
     out.flatness = flatness_of(N, H);
-    out.kl_divergence = kl_of(N, H, h->width_prev);
+    out.kl_divergence = kl_of(N, H, h->reach_prev);
+    out.width = (uint32_t)width_of(N, H);
     out.chebyshev = chebyshev_of(N, H);
     out.kernel_ms = kernel_ms;
     out.kernel_launches = launches;
     out.kernel_variant = variant;
-    h->width_prev = width_of(N, H);
+    h->width_prev = (int)out.width;
+    h->reach_prev = reach_of(N, H);
     if (update) {
         // Eq. 4, W <- W / H, in logarithmic form; empty bins keep omega.
         for (uint32_t k = 0; k <= N; ++k)
@@ -316,19 +335,65 @@ void release(muca_instance* h)
     delete h;
 }
 
-// therm unrecorded sweeps, then `sweeps` recorded ones; H -> h->hist.
-int run_sweeps(muca_instance* h, uint32_t therm, uint32_t sweeps, bool update, muca_info* info)
+// One piece of a call: whole sweeps [sweep0, sweep0 + n) of which the first
+// `therm` are not recorded, or (n == 0) the sites [site_begin, site_end) of
+// sweep sweep0 with recording from site rec_begin on.
+struct Segment {
+    uint64_t sweep0;
+    uint64_t n;
+    uint64_t therm;
+    uint32_t site_begin, site_end, rec_begin;
+};
+
+// Cuts the attempts [pos0, pos0 + therm + recorded) -- recording from
+// pos0 + therm on -- into whole-sweep runs for the sweep kernels and partial
+// sweeps for the range kernel.  A sweep that holds the start of recording is
+// run as a partial sweep unless recording starts at its first site.
+std::vector<Segment> segments_of(uint64_t N, uint64_t pos0, uint64_t therm, uint64_t recorded)
+{
+    std::vector<Segment> out;
+    const uint64_t rec = pos0 + therm, end = rec + recorded;
+    uint64_t p = pos0;
+    while (p < end) {
+        const uint64_t sweep = p / N, base = sweep * N;
+        const uint64_t sweep_end = base + N;
+        const bool partial = p != base || end < sweep_end || (rec > p && rec < sweep_end);
+        if (partial) {
+            const uint64_t e = std::min(end, sweep_end);
+            const uint64_t rb = std::min(std::max(rec, p), e);
+            out.push_back(Segment{sweep, 0, 0, (uint32_t)(p - base), (uint32_t)(e - base),
+                                  (uint32_t)(rb - base)});
+            p = e;
+            continue;
+        }
+        // whole sweeps up to the end, or up to the sweep holding the start of
+        // recording when that start is not on a sweep boundary
+        uint64_t n = (end - p) / N;
+        if (rec > p && (rec - p) % N != 0)
+            n = std::min(n, (rec - p) / N);
+        const uint64_t th = rec > p ? std::min(n, (rec - p) / N) : 0;
+        out.push_back(Segment{sweep, n, th, 0, 0, 0});
+        p += n * N;
+    }
+    return out;
+}
+
+// therm unrecorded, then `recorded` recorded attempts per walker, starting at
+// the instance's position; H -> h->hist.
+int run_attempts(muca_instance* h, uint64_t therm, uint64_t recorded, bool update, muca_info* info)
 {
     int rc = check_live(h);
     if (rc != MUCA_OK)
         return rc;
     const uint32_t N = h->N;
-    const uint64_t total = (uint64_t)therm + sweeps;
-    const long double attempts_ld = (long double)h->p.walkers * N * (long double)total;
+    const uint64_t total = therm + recorded;
+    if (total < therm)
+        return fail(h, MUCA_ERR_OVERFLOW, "attempt count wraps");
+    const long double attempts_ld = (long double)h->p.walkers * (long double)total;
     if (attempts_ld >= 18446744073709551615.0L)
-        return fail(h, MUCA_ERR_OVERFLOW, "walkers * N * sweeps exceeds 2^64");
-    if (h->sweep_counter + total < h->sweep_counter)
-        return fail(h, MUCA_ERR_OVERFLOW, "sweep counter would wrap");
+        return fail(h, MUCA_ERR_OVERFLOW, "walkers * attempts exceeds 2^64");
+    if (h->position + total < h->position)
+        return fail(h, MUCA_ERR_OVERFLOW, "attempt position would wrap");
 
     compute_thresholds(N, h->omega.data(), h->table5.data());
     // kernel choice: 2 split, 1 fast, 0 generic (all give the same bits)
@@ -362,40 +427,61 @@ int run_sweeps(muca_instance* h, uint32_t therm, uint32_t sweeps, bool update, m
         chunk = cap;
     uint32_t launches = 0;
     MUCA_HIP(h, hipEventRecord(h->ev_start, h->stream), "hipEventRecord");
-    for (uint64_t s0 = 0; s0 < total; s0 += chunk) {
-        const uint32_t n = (uint32_t)((total - s0) < chunk ? (total - s0) : chunk);
-        const uint32_t th = s0 >= therm ? 0u : (uint32_t)((therm - s0) < n ? (therm - s0) : n);
-        if (fast) {
-            muca::FastSweepArgs a{};
-            a.spins = h->d_spins;
-            a.energy = h->d_energy;
-            a.table = reinterpret_cast<const uint32_t*>(h->d_table);
-            a.hist = h->d_hist;
-            a.sweep0 = h->sweep_counter + s0;
-            a.wpad = h->wpad;
-            a.walkers = h->p.walkers;
-            a.seed = h->p.seed;
-            a.nsweeps = n;
-            a.therm = th;
-            MUCA_HIP(h,
-                     variant == 2 ? muca::launch_split_sweep(h->L, a, h->stream)
-                                  : muca::launch_fast_sweep(h->L, a, h->stream),
-                     "sweep launch");
-        } else {
-            muca::SweepArgs a{};
+    for (const Segment& g : segments_of(N, h->position, therm, recorded)) {
+        if (g.n == 0) {
+            muca::RangeArgs a{};
             a.spins = h->d_spins;
             a.energy = h->d_energy;
             a.table = h->d_table;
             a.hist = h->d_hist;
-            a.sweep0 = h->sweep_counter + s0;
+            a.sweep = g.sweep0;
+            a.L = h->L;
             a.wpad = h->wpad;
             a.walkers = h->p.walkers;
             a.seed = h->p.seed;
-            a.nsweeps = n;
-            a.therm = th;
-            MUCA_HIP(h, muca::launch_sweep(h->L, a, h->stream), "sweep launch");
+            a.site_begin = g.site_begin;
+            a.site_end = g.site_end;
+            a.rec_begin = g.rec_begin;
+            a.fast_table = fast ? 1u : 0u;
+            MUCA_HIP(h, muca::launch_sweep_range(a, h->stream), "partial sweep launch");
+            ++launches;
+            continue;
         }
-        ++launches;
+        for (uint64_t s0 = 0; s0 < g.n; s0 += chunk) {
+            const uint32_t n = (uint32_t)std::min<uint64_t>(g.n - s0, chunk);
+            const uint32_t th = s0 >= g.therm ? 0u : (uint32_t)std::min<uint64_t>(g.therm - s0, n);
+            if (fast) {
+                muca::FastSweepArgs a{};
+                a.spins = h->d_spins;
+                a.energy = h->d_energy;
+                a.table = reinterpret_cast<const uint32_t*>(h->d_table);
+                a.hist = h->d_hist;
+                a.sweep0 = g.sweep0 + s0;
+                a.wpad = h->wpad;
+                a.walkers = h->p.walkers;
+                a.seed = h->p.seed;
+                a.nsweeps = n;
+                a.therm = th;
+                MUCA_HIP(h,
+                         variant == 2 ? muca::launch_split_sweep(h->L, a, h->stream)
+                                      : muca::launch_fast_sweep(h->L, a, h->stream),
+                         "sweep launch");
+            } else {
+                muca::SweepArgs a{};
+                a.spins = h->d_spins;
+                a.energy = h->d_energy;
+                a.table = h->d_table;
+                a.hist = h->d_hist;
+                a.sweep0 = g.sweep0 + s0;
+                a.wpad = h->wpad;
+                a.walkers = h->p.walkers;
+                a.seed = h->p.seed;
+                a.nsweeps = n;
+                a.therm = th;
+                MUCA_HIP(h, muca::launch_sweep(h->L, a, h->stream), "sweep launch");
+            }
+            ++launches;
+        }
     }
     MUCA_HIP(h, hipEventRecord(h->ev_stop, h->stream), "hipEventRecord");
     MUCA_HIP(h, hipMemcpyAsync(h->h_hist, h->d_hist, h->lay.hist_bytes, hipMemcpyDeviceToHost,
@@ -407,7 +493,7 @@ int run_sweeps(muca_instance* h, uint32_t therm, uint32_t sweeps, bool update, m
         MUCA_HIP(h, hipEventElapsedTime(&ms, h->ev_start, h->ev_stop), "hipEventElapsedTime");
 
     std::memcpy(h->hist.data(), h->h_hist, h->lay.hist_bytes);
-    return finish_call(h, therm, sweeps, update, ms, launches, variant, info);
+    return finish_call(h, therm, recorded, update, ms, launches, variant, info);
 }
 
 }  // namespace
@@ -537,12 +623,78 @@ int muca_destroy(muca_instance* h)
 
 int muca_iterate(muca_instance* h, uint32_t therm_sweeps, uint32_t sweeps, muca_info* info)
 {
-    return run_sweeps(h, therm_sweeps, sweeps, true, info);
+    if (!h)
+        return MUCA_ERR_INVALID_ARG;
+    return run_attempts(h, (uint64_t)therm_sweeps * h->N, (uint64_t)sweeps * h->N, true, info);
 }
 
 int muca_production(muca_instance* h, uint32_t therm_sweeps, uint32_t sweeps, muca_info* info)
 {
-    return run_sweeps(h, therm_sweeps, sweeps, false, info);
+    if (!h)
+        return MUCA_ERR_INVALID_ARG;
+    return run_attempts(h, (uint64_t)therm_sweeps * h->N, (uint64_t)sweeps * h->N, false, info);
+}
+
+int muca_iterate_attempts(muca_instance* h, uint64_t therm_attempts, uint64_t attempts, muca_info* info)
+{
+    return run_attempts(h, therm_attempts, attempts, true, info);
+}
+
+int muca_production_attempts(muca_instance* h, uint64_t therm_attempts, uint64_t attempts,
+                             muca_info* info)
+{
+    return run_attempts(h, therm_attempts, attempts, false, info);
+}
+
+int muca_run_schedule(muca_instance* h, const muca_schedule* sc, muca_schedule_step* steps,
+                      uint32_t max_steps, uint32_t* iterations)
+{
+    if (iterations)
+        *iterations = 0;
+    if (int rc = check_live(h))
+        return rc;
+    if (!sc || !(sc->z > 0.0) || !(sc->growth >= 1.0) || !(sc->dk_flat > 0.0) || sc->max_iterations == 0)
+        return fail(h, MUCA_ERR_INVALID_ARG, "schedule needs z > 0, growth >= 1, dk_flat > 0, max_iterations > 0");
+    if (steps == nullptr && max_steps != 0)
+        return fail(h, MUCA_ERR_INVALID_ARG, "steps is NULL");
+    const uint32_t N = h->N;
+    const double walkers = (double)h->p.walkers;
+    double x = 0.0;
+    bool full = false;
+    for (uint32_t it = 0; it < sc->max_iterations; ++it) {
+        // Sec. 3: w = max(w', w_min), w' the range the previous iteration covered
+        const uint32_t w = std::max<uint32_t>((uint32_t)h->width_prev, sc->w_min);
+        if (full) {
+            x = x * sc->growth;
+        } else {
+            x = 6.0 * std::pow((double)w, sc->z) / walkers;  // Eq. 7
+            full = w == N + 1;
+        }
+        if (!(x < 1.8e19))
+            return fail(h, MUCA_ERR_OVERFLOW, "update count of the schedule passes 2^64");
+        const uint64_t updates = (uint64_t)std::floor(x) + 1;
+        const uint64_t therm = (uint64_t)sc->f_therm * w;
+        muca_info info{};
+        if (int rc = run_attempts(h, therm, updates, true, &info))
+            return rc;
+        if (iterations)
+            *iterations = it + 1;
+        if (it < max_steps) {
+            muca_schedule_step st{};
+            st.therm_attempts = therm;
+            st.update_attempts = updates;
+            st.kl_divergence = info.kl_divergence;
+            st.chebyshev = info.chebyshev;
+            st.flatness = info.flatness;
+            st.kernel_ms = info.kernel_ms;
+            st.width = w;
+            st.covered = info.width;
+            steps[it] = st;
+        }
+        if (full && info.kl_divergence < sc->dk_flat)
+            return MUCA_OK;
+    }
+    return fail(h, MUCA_ERR_NOT_CONVERGED, "the schedule reached max_iterations");
 }
 
 int muca_histogram(const muca_instance* h, uint64_t* out, size_t n_bins)

@@ -97,6 +97,33 @@ class Solver:
         self._check(self._lib.muca_production(self._h, therm_sweeps, sweeps, ctypes.byref(info)))
         return info.as_dict()
 
+    def iterate_attempts(self, therm_attempts, attempts):
+        """A weight iteration counted in attempted flips per walker; it may
+        start and stop inside a sweep."""
+        info = _abi.MucaInfo()
+        self._check(self._lib.muca_iterate_attempts(self._h, therm_attempts, attempts,
+                                                    ctypes.byref(info)))
+        return info.as_dict()
+
+    def production_attempts(self, therm_attempts, attempts):
+        info = _abi.MucaInfo()
+        self._check(self._lib.muca_production_attempts(self._h, therm_attempts, attempts,
+                                                       ctypes.byref(info)))
+        return info.as_dict()
+
+    def run_schedule(self, z=2.25, growth=1.1, dk_flat=1e-4, f_therm=30, w_min=10,
+                     max_iterations=1000):
+        """The paper's iteration schedule (Sec. 3) to its stop rule.
+        Returns (converged, [step dicts])."""
+        sc = _abi.Schedule(z, growth, dk_flat, f_therm, w_min, max_iterations, 0)
+        steps = (_abi.ScheduleStep * max_iterations)()
+        n = ctypes.c_uint32()
+        rc = self._lib.muca_run_schedule(self._h, ctypes.byref(sc), steps, max_iterations,
+                                         ctypes.byref(n))
+        if rc not in (_abi.MUCA_OK, _abi.MUCA_ERR_NOT_CONVERGED):
+            self._check(rc)
+        return rc == _abi.MUCA_OK, [steps[i].as_dict() for i in range(n.value)]
+
     # ---------------------------------------------------------------- outputs
     def histogram(self):
         out = np.zeros(self.N + 1, dtype=np.uint64)

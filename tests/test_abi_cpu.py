@@ -72,7 +72,8 @@ def test_struct_layouts_match_header(tmp_path):
     from paper_1707_00919_amd import _abi
     structs = {"muca_params": _abi.MucaParams, "muca_info": _abi.MucaInfo,
                "muca_server_config": _abi.ServerConfig, "muca_request": _abi.Request,
-               "muca_result": _abi.Result, "muca_server_counters": _abi.ServerCounters}
+               "muca_result": _abi.Result, "muca_server_counters": _abi.ServerCounters,
+               "muca_schedule": _abi.Schedule, "muca_schedule_step": _abi.ScheduleStep}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "muca.h"', 'int main(void){']
     for cname, py in structs.items():
         lines.append('printf("%s size %%zu\\n", sizeof(%s));' % (cname, cname))

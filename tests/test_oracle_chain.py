@@ -71,6 +71,44 @@ def test_split_calls_equal_one_call():
     assert hb == int(a.hist.sum())
 
 
+def test_attempt_order_is_typewriter():
+    # omega = 0 accepts every proposal, so after attempts 0 .. a-1 exactly the
+    # sites 0 .. a-1 (p mod N, row by row) are flipped; later calls continue
+    # at the next site and wrap into the next sweep.
+    L, W = 6, 7
+    N = L * L
+    o = oracle.OracleMuca(L, W, 4)
+    s0 = o.spins.copy()
+    flipped = np.zeros(N, dtype=bool)
+    for therm, count in [(0, 5), (3, 0), (2, 11), (0, N), (7, 2 * N + 3)]:
+        info = o.production_attempts(therm, count)
+        for p in range(o.position - therm - count, o.position):
+            flipped[p % N] ^= True
+        assert info["hist_sum"] == W * count and info["position"] == o.position
+        assert np.array_equal(o.spins, np.where(flipped, -s0, s0))
+        for w in range(W):
+            assert o.energies[w] == oracle.energy(L, o.spins[w])
+
+
+def test_attempt_split_calls_equal_one_call():
+    # any cut of a run into calls, inside sweeps or not, gives the same chain
+    L = 8
+    N = L * L
+    om = random_log_weights(L, 6, scale=2.0)
+    a = oracle.OracleMuca(L, 20, 9)
+    a.set_log_weights(om)
+    a.production_attempts(0, 5 * N + 17)
+    b = oracle.OracleMuca(L, 20, 9)
+    b.set_log_weights(om)
+    total = 0
+    for cut in [1, N - 2, 3, 2 * N, 0, N + 5, 5 * N + 17 - (1 + N - 2 + 3 + 2 * N + N + 5)]:
+        total += b.production_attempts(0, cut)["hist_sum"]
+    assert b.position == a.position == 5 * N + 17
+    assert np.array_equal(a.spins, b.spins)
+    assert np.array_equal(a.energies, b.energies)
+    assert total == int(a.hist.sum())
+
+
 def test_walker_population_and_threads_do_not_change_results():
     om = random_log_weights(6, 8, scale=2.0)
     runs = []

@@ -154,6 +154,20 @@ def test_chebyshev_and_kl():
     f2 = np.zeros(N + 1, dtype=np.uint64)
     f2[3] = 5
     assert abs(oracle.kl_divergence(f2, 1) - math.log(10.0)) < 1e-15
+    # the full range spans N + 1 bins of which N - 1 are reachable: a
+    # histogram flat on the reachable bins has d_k = 0 against Q = 1/(N-1)
+    full = np.zeros(N + 1, dtype=np.uint64)
+    full[oracle.reachable_mask(N)] = 9
+    assert oracle.width(full) == N + 1
+    assert oracle.reachable_width(full) == N - 1
+    assert abs(oracle.kl_divergence(full, N - 1)) < 1e-15
+    # against a Q on more bins than P fills, d_k = ln(w / n) for P flat on n
+    assert abs(oracle.kl_divergence(f, 24) - math.log(2.0)) < 1e-15
+    assert oracle.reachable_width(f) == 12          # bins 2..13 hold no forbidden bin
+    g = np.zeros(N + 1, dtype=np.uint64)
+    g[[0, 2, 3]] = 4                                # range 0..3 holds forbidden bin 1
+    assert oracle.width(g) == 4 and oracle.reachable_width(g) == 3
+
 
 
 # -------------------------------------------------------------------- ln g
