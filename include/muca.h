@@ -226,6 +226,32 @@ int muca_last_info(const muca_instance* h, muca_info* out);
 const char* muca_last_error(const muca_instance* h);
 
 /* ------------------------------------------------------------------------
+ * Production analysis (host only; no device is touched).  A production run
+ * at fixed weights omega cut into `blocks` calls gives one histogram per call
+ * (the paper uses 100, Sec. 3.3); block_hists holds them one after another,
+ * blocks * (L*L+1) counts.  Estimates use the summed histogram; error bars
+ * are jackknife errors over the blocks, sqrt((B-1)/B sum_b (x_(b) - x_.)^2)
+ * with x_(b) the estimate without block b (0 when blocks == 1).
+ * ------------------------------------------------------------------------ */
+
+/* ln g (normalisation as in muca_log_dos) and its jackknife error per bin
+ * (ln_g_err may be NULL).  Bins with no entries get ln g = -inf and error
+ * NaN; a bin that is empty once some block is left out gets error +inf.
+ * ln_g and ln_g_err hold L*L+1 values.  MUCA_ERR_NOT_CONVERGED if the
+ * normalisation's anchor is missing from the summed histogram.              */
+int muca_jackknife_log_dos(uint32_t L, uint32_t blocks, const uint64_t* block_hists,
+                           const double* omega, int normalization, double* ln_g, double* ln_g_err);
+
+/* Canonical averages by reweighting the production run (Sec. 2.1: the
+ * canonical distribution is g(E) e^{-beta E} / Z_beta): per inverse
+ * temperature betas[j], energy[j] = <E>/N and specific_heat[j] =
+ * beta^2 (<E^2> - <E>^2) / N (J = k_B = 1), with jackknife errors (the
+ * *_err arrays may be NULL).                                                */
+int muca_canonical(uint32_t L, uint32_t blocks, const uint64_t* block_hists, const double* omega,
+                   uint32_t n_beta, const double* betas, double* energy, double* energy_err,
+                   double* specific_heat, double* specific_heat_err);
+
+/* ------------------------------------------------------------------------
  * Batched form: many independent instances (any mix of L and walker counts)
  * swept together so that their walkers fill the device.  The method is the
  * same per instance (Sec. 2.2: independent walker populations, each with its

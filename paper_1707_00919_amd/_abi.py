@@ -123,6 +123,8 @@ PROTOTYPES = {
                                         ctypes.POINTER(MucaInfo)]),
     "muca_run_schedule": (_INT, [_P, ctypes.POINTER(Schedule), ctypes.POINTER(ScheduleStep), _U32,
                                  ctypes.POINTER(_U32)]),
+    "muca_jackknife_log_dos": (_INT, [_U32, _U32, _P, _P, _INT, _P, _P]),
+    "muca_canonical": (_INT, [_U32, _U32, _P, _P, _U32, _P, _P, _P, _P, _P]),
     "muca_batch_create": (_INT, [ctypes.POINTER(_P), _U32, _P, _U32, ctypes.POINTER(_P)]),
     "muca_batch_run": (_INT, [_P, _P, _P, _P, ctypes.POINTER(MucaInfo)]),
     "muca_batch_set_members": (_INT, [_P, ctypes.POINTER(_P), _U32]),

@@ -31,6 +31,10 @@ void device_table(uint32_t N, const uint64_t* t5, uint64_t* t4);
 bool fast_table(uint32_t N, const uint64_t* t5, uint32_t* f);
 double flatness_of(uint32_t N, const uint64_t* H);
 double chebyshev_of(uint32_t N, const uint64_t* H);
+// ln g[k] = ln H[k] - omega[k] + c on reachable bins with H > 0, -inf
+// elsewhere; normalization 0: ln g[0] = ln 2, 1: sum exp(ln g) = 2^N.
+// Returns 0, or 1 (ground-state bin empty) / 2 (histogram empty).
+int log_dos_of(uint32_t N, const uint64_t* H, const double* omega, int normalization, double* out);
 // Eq. 6 with Q uniform over max(reach_prev, 10) bins.
 double kl_of(uint32_t N, const uint64_t* H, int reach_prev);
 // Reachable bins (not 1 or N-1) between the lowest and highest visited bin.

@@ -248,6 +248,38 @@ int width_of(uint32_t N, const uint64_t* H)
     return lo < 0 ? 0 : hi - lo + 1;
 }
 
+int log_dos_of(uint32_t N, const uint64_t* H, const double* omega, int normalization, double* out)
+{
+    double mx = -INFINITY;
+    for (uint32_t k = 0; k <= N; ++k) {
+        if (k != 1 && k != N - 1 && H[k] > 0) {
+            out[k] = std::log((double)H[k]) - omega[k];
+            if (out[k] > mx)
+                mx = out[k];
+        } else {
+            out[k] = -INFINITY;
+        }
+    }
+    double c;
+    if (normalization == 0) {
+        if (H[0] == 0)
+            return 1;
+        c = std::log(2.0) - out[0];
+    } else {
+        if (mx == -INFINITY)
+            return 2;
+        double s = 0.0;
+        for (uint32_t k = 0; k <= N; ++k)
+            if (out[k] != -INFINITY)
+                s += std::exp(out[k] - mx);
+        c = (double)N * std::log(2.0) - (mx + std::log(s));
+    }
+    for (uint32_t k = 0; k <= N; ++k)
+        if (out[k] != -INFINITY)
+            out[k] += c;
+    return 0;
+}
+
 int finish_call(muca_instance* h, uint64_t therm, uint64_t recorded, bool update, double kernel_ms,
                 uint32_t launches, uint32_t variant, muca_info* info)
 {
@@ -799,35 +831,14 @@ int muca_log_dos(const muca_instance* h, int normalization, double* out, size_t 
     const uint32_t N = h->N;
     if (!out || n != (size_t)N + 1 || (normalization != 0 && normalization != 1))
         return fail(m, MUCA_ERR_INVALID_ARG, "n must be L*L+1 and normalization 0 or 1");
-    const uint64_t* H = h->hist.data();
-    double mx = -INFINITY;
-    for (uint32_t k = 0; k <= N; ++k) {
-        if (reachable(N, k) && H[k] > 0) {
-            out[k] = std::log((double)H[k]) - h->omega[k];
-            if (out[k] > mx)
-                mx = out[k];
-        } else {
-            out[k] = -INFINITY;
-        }
+    switch (log_dos_of(N, h->hist.data(), h->omega.data(), normalization, out)) {
+    case 1:
+        return fail(m, MUCA_ERR_NOT_CONVERGED, "ground-state bin is empty");
+    case 2:
+        return fail(m, MUCA_ERR_NOT_CONVERGED, "histogram is empty");
+    default:
+        return MUCA_OK;
     }
-    double c;
-    if (normalization == 0) {
-        if (H[0] == 0)
-            return fail(m, MUCA_ERR_NOT_CONVERGED, "ground-state bin is empty");
-        c = std::log(2.0) - out[0];
-    } else {
-        if (mx == -INFINITY)
-            return fail(m, MUCA_ERR_NOT_CONVERGED, "histogram is empty");
-        double s = 0.0;
-        for (uint32_t k = 0; k <= N; ++k)
-            if (out[k] != -INFINITY)
-                s += std::exp(out[k] - mx);
-        c = (double)N * std::log(2.0) - (mx + std::log(s));
-    }
-    for (uint32_t k = 0; k <= N; ++k)
-        if (out[k] != -INFINITY)
-            out[k] += c;
-    return MUCA_OK;
 }
 
 int muca_last_info(const muca_instance* h, muca_info* out)
