@@ -193,6 +193,214 @@ def cpu_baseline(wl, ln_g, sweeps, warm):
     }
 
 
+# ------------------------------------------------------------ other workloads
+def _solo_solve(Solver, L, W, seed, iter_sweeps, min_flat, max_it, prod_therm, prod_sweeps):
+    s = Solver(L, W, seed)
+    att, it = 0, 0
+    while it < max_it:
+        info = s.iterate(0, iter_sweeps)
+        att += info["attempts"]
+        it += 1
+        if info["flatness"] >= min_flat:
+            break
+    att += s.production(prod_therm, prod_sweeps)["attempts"]
+    lng = _log_dos_or_zeros(s)
+    s.close()
+    return att, it, lng
+
+
+def _log_dos_or_zeros(s):
+    from paper_1707_00919_amd import MucaError
+    try:
+        return s.log_dos(0)
+    except MucaError:
+        return np.zeros(s.N + 1)
+
+
+def bench_batched(args):
+    """48 instances of uneven size (muca_inputs.batch_instances) solved in
+    batched rounds, against the same instances solved one per launch."""
+    import torch
+    from paper_1707_00919_amd import Batch, Solver, _abi
+    from muca_inputs import BATCH_WORKLOAD as C, batch_instances
+    inst = batch_instances(C["instances"])
+    flags = _abi.MUCA_BATCH_GRAPH | _abi.MUCA_BATCH_AUTOTUNE
+
+    def batched():
+        members = [Solver(L, W, sd) for L, W, sd in inst]
+        b = Batch(members, flags=flags)
+        n = len(members)
+        iters = [0] * n
+        done = [False] * n
+        att = 0
+        kernel_ms = 0.0
+        rounds = 0
+        while not all(done):
+            infos = b.run([0 if d else 1 for d in done], 0, C["iter_sweeps"])
+            rounds += 1
+            kernel_ms += next(i for i in infos if i is not None)["kernel_ms"]
+            for i, inf in enumerate(infos):
+                if inf is None:
+                    continue
+                att += inf["attempts"]
+                iters[i] += 1
+                if inf["flatness"] >= C["min_flat"] or iters[i] >= C["max_iterations"]:
+                    done[i] = True
+        infos = b.run([2] * n, C["prod_therm_sweeps"], C["prod_sweeps"])
+        kernel_ms += infos[0]["kernel_ms"]
+        att += sum(i["attempts"] for i in infos)
+        lngs = [_log_dos_or_zeros(m) for m in members]
+        b.close()
+        for m in members:
+            m.close()
+        return att, iters, lngs, rounds, kernel_ms
+
+    for _ in range(args.warmup):
+        batched()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    att_b, iters_b, lng_b, rounds, kms = batched()
+    torch.cuda.synchronize()
+    wall_b = time.perf_counter() - t0
+    print("batched: %.2f s, %d rounds" % (wall_b, rounds), file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    att_s, same = 0, True
+    iters_s = []
+    for (L, W, sd), lb in zip(inst, lng_b):
+        a, it, lng = _solo_solve(Solver, L, W, sd, C["iter_sweeps"], C["min_flat"],
+                                 C["max_iterations"], C["prod_therm_sweeps"], C["prod_sweeps"])
+        att_s += a
+        iters_s.append(it)
+        same &= bool(np.array_equal(lng.view(np.uint64), lb.view(np.uint64)))
+    torch.cuda.synchronize()
+    wall_s = time.perf_counter() - t0
+    print("one per launch: %.2f s" % wall_s, file=sys.stderr, flush=True)
+    out = {
+        "metric": "aggregate spin-flip attempts/s, 48 uneven instances, batched rounds",
+        "value": att_b / wall_b, "unit": "attempts/s", "n_gpus": 1, "steps": 1,
+        "warmup": args.warmup, "ms_per_step": wall_b * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": "batched48", "instances": len(inst),
+                   "L": sorted(set(L for L, _, _ in inst)),
+                   "walkers_total": sum(W for _, W, _ in inst),
+                   "iter_sweeps": C["iter_sweeps"], "min_flatness": C["min_flat"],
+                   "production": [C["prod_therm_sweeps"], C["prod_sweeps"]],
+                   "batch_flags": "graph|autotune"},
+        "one_per_launch_attempts_per_s": att_s / wall_s,
+        "speedup_vs_one_per_launch": (att_b / wall_b) / (att_s / wall_s),
+        "bit_identical_to_one_per_launch": same and iters_b == iters_s,
+        "rounds": rounds, "iterations_max": max(iters_b),
+        "batched_wall_s": wall_b, "one_per_launch_wall_s": wall_s,
+        "batched_device_ms": kms,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_served(args):
+    """Poisson request arrivals (muca_inputs.serving_requests) into the
+    continuous-batching server; request latency percentiles and throughput."""
+    import torch
+    from paper_1707_00919_amd import Server
+    from muca_inputs import SERVE_REQUEST as Q, serving_requests
+    reqs = serving_requests(duration=args.serve_duration)
+    srv = Server(64 << 30, max_active_walkers=args.serve_max_walkers, batch_flags=1)
+    t0 = time.perf_counter()
+    tickets = {}
+    nxt = 0
+    results = {}
+    last_note = t0
+    while len(results) < len(reqs):
+        now = time.perf_counter() - t0
+        while nxt < len(reqs) and reqs[nxt][0] <= now:
+            _, L, W, sd = reqs[nxt]
+            tickets[srv.submit(L, W, sd, **Q)] = nxt
+            nxt += 1
+        if not srv.progress():
+            time.sleep(2e-4)
+        for t in list(tickets):
+            r = srv.take(t)
+            if r is not None:
+                results[tickets.pop(t)] = r[0]
+        if time.perf_counter() - last_note > 30.0:
+            st = srv.stats()
+            print("served %d/%d, active %d, queued %d, %.0f s" %
+                  (len(results), len(reqs), st["active"], st["queued"], st["clock_s"]),
+                  file=sys.stderr, flush=True)
+            last_note = time.perf_counter()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    st = srv.stats()
+    srv.close()
+    lat = [r["t_done"] - r["t_submit"] for r in results.values()]
+    ttcw = [r["t_weights"] - r["t_submit"] for r in results.values()]
+    att = sum(r["attempts"] for r in results.values())
+    out = {
+        "metric": "served multicanonical solves: aggregate attempts/s; p50/p99 latency",
+        "value": att / wall, "unit": "attempts/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": wall * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": "served_poisson20", "requests": len(reqs),
+                   "arrival_rate_per_s": 20.0, "arrival_window_s": args.serve_duration,
+                   "L": [16, 24, 32, 48, 64], "walkers": [1024, 16384],
+                   "mem_cap_bytes": 64 << 30, "max_active_walkers": args.serve_max_walkers,
+                   **Q},
+        "latency_p50_s": nearest_rank(lat, 50), "latency_p99_s": nearest_rank(lat, 99),
+        "ttcw_p50_s": nearest_rank(ttcw, 50), "ttcw_p99_s": nearest_rank(ttcw, 99),
+        "converged": sum(1 for r in results.values() if r["status"] == 0),
+        "failed": sum(1 for r in results.values() if r["status"] not in (0, 5)),
+        "makespan_s": wall, "peak_counters": st,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_schedule(args):
+    """The paper's iteration schedule (Sec. 3: Eq. 7 update counts, f_therm
+    = 30, growth 1.1, stop at d_k < 1e-4) at L = 32, 16384 walkers, then a
+    production run; time to converged weights and ln g accuracy."""
+    import torch
+    from paper_1707_00919_amd import Solver
+    L, W = 32, 16384
+    ln_g = exact_ln_g(L)
+    runs = []
+    for seed in range(1, args.steps + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s = Solver(L, W, seed)
+        ok, steps = s.run_schedule(max_iterations=1000)
+        t_w = time.perf_counter() - t0
+        s.production(10000, 10000)
+        lng = s.log_dos(0)
+        wall = time.perf_counter() - t0
+        m = np.isfinite(ln_g)
+        pos = s.last_info()["position"]
+        s.close()
+        runs.append(dict(ok=ok, iterations=len(steps), ttcw=t_w, wall=wall,
+                         err=float(np.max(np.abs(lng[m] - ln_g[m]))), position=pos,
+                         first_full=next((i for i, st in enumerate(steps)
+                                          if st["width"] == L * L + 1), None),
+                         attempts=W * pos))
+        print("seed %d: converged %s, %d iterations, %.2f s to weights, ln g err %.3f" %
+              (seed, ok, len(steps), t_w, runs[-1]["err"]), file=sys.stderr, flush=True)
+    wall = sum(r["wall"] for r in runs)
+    out = {
+        "metric": "time to converged weights, paper's schedule, L=32, 16384 walkers",
+        "value": nearest_rank([r["ttcw"] for r in runs], 50), "unit": "s", "n_gpus": 1,
+        "steps": len(runs), "warmup": 0, "ms_per_step": wall * 1e3 / len(runs),
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": "paper_schedule_L32", "L": L, "walkers": W, "z": 2.25,
+                   "f_therm": 30, "growth": 1.1, "dk_flat": 1e-4, "production": [10000, 10000]},
+        "ttcw_p50_s": nearest_rank([r["ttcw"] for r in runs], 50),
+        "ttcw_p99_s": nearest_rank([r["ttcw"] for r in runs], 99),
+        "iterations": [r["iterations"] for r in runs],
+        "first_full_range_iteration": [r["first_full"] for r in runs],
+        "converged": sum(r["ok"] for r in runs),
+        "ln_g_max_abs_err": max(r["err"] for r in runs),
+        "attempts_per_s": sum(r["attempts"] for r in runs) / wall,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -202,6 +410,12 @@ def main():
     ap.add_argument("--cpu-sweeps", type=int, default=40)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-hardware-rate", action="store_true")
+    ap.add_argument("--workload", default=WORKLOAD,
+                    choices=[WORKLOAD, "batched48", "served_poisson20", "paper_schedule_L32"],
+                    help="the headline workload (default) or one of the batched, served "
+                         "and paper-schedule workloads, each with its own JSON line")
+    ap.add_argument("--serve-duration", type=float, default=60.0)
+    ap.add_argument("--serve-max-walkers", type=int, default=1 << 17)
     ap.add_argument("--profile-pass", action="store_true",
                     help="short sweep + calibration copy for rocprofv3 counter runs")
     args = ap.parse_args()
@@ -217,6 +431,12 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
     torch.cuda.set_device(0)
+    if args.workload == "batched48":
+        return bench_batched(args)
+    if args.workload == "served_poisson20":
+        return bench_served(args)
+    if args.workload == "paper_schedule_L32":
+        return bench_schedule(args)
     wl = WORKLOADS[WORKLOAD]
     ln_g = exact_ln_g(wl["L"])
     if args.profile_pass:

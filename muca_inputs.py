@@ -83,3 +83,30 @@ def batch_instances(count=48, rng_seed=0):
     Ls = rng.choice(np.array(BATCH_LS), size=count)
     walkers = np.rint(np.exp(rng.uniform(np.log(256.0), np.log(8192.0), size=count))).astype(int)
     return [(int(L), int(W), i + 1) for i, (L, W) in enumerate(zip(Ls, walkers))]
+
+
+# The serving workload: Poisson arrivals at SERVE_RATE requests/s for
+# SERVE_DURATION s from default_rng(1) (exponential gaps, then per request L
+# uniform from SERVE_LS and walkers log-uniform on [1024, 16384]); request i
+# has seed 1000 + i.  Each request iterates with 200-sweep iterations to
+# flatness 0.5, then runs 2000 unrecorded and 2000 recorded production sweeps.
+SERVE_LS = (16, 24, 32, 48, 64)
+SERVE_RATE = 20.0
+SERVE_DURATION = 60.0
+SERVE_REQUEST = dict(iter_sweeps=200, min_flatness=0.5, max_iterations=2000, prod_therm=2000,
+                     prod_sweeps=2000)
+
+
+def serving_requests(rate=SERVE_RATE, duration=SERVE_DURATION, rng_seed=1):
+    """[(arrival_s, L, walkers, seed)] of the serving workload."""
+    rng = np.random.default_rng(rng_seed)
+    t = 0.0
+    out = []
+    while True:
+        t += rng.exponential(1.0 / rate)
+        if t >= duration:
+            break
+        L = int(rng.choice(np.array(SERVE_LS)))
+        W = int(np.rint(np.exp(rng.uniform(np.log(1024.0), np.log(16384.0)))))
+        out.append((t, L, W, 1000 + len(out)))
+    return out
