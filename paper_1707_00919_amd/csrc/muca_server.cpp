@@ -126,7 +126,8 @@ struct Lane {
     uint32_t L = 0;
     hipStream_t stream = nullptr;
     muca_batch* batch = nullptr;
-    std::vector<Request*> members;
+    std::vector<Request*> members;  // the batch's members, in its order
+    std::vector<Request*> joining;  // admitted while a round ran; join the next one
     bool dirty = true;  // membership changed since the batch last saw it
     bool in_flight = false;
     std::vector<uint32_t> mode, therm, sweeps;
@@ -259,8 +260,7 @@ int admit(muca_server* s)
         ++s->admitted;
         Lane& lane = s->lanes[r->q.L];
         lane.L = r->q.L;
-        lane.members.push_back(r);
-        lane.dirty = true;
+        lane.joining.push_back(r);
     }
     return MUCA_OK;
 }
@@ -268,11 +268,15 @@ int admit(muca_server* s)
 // Host half of a finished lane round: advance every member's schedule.
 void lane_collect(muca_server* s, Lane& lane, const std::vector<muca_info>& infos, int rc)
 {
+    // lane.members are exactly the members of the round that ended (joiners
+    // wait in lane.joining), so infos, mode, therm and sweeps line up with them
     std::vector<Request*> keep;
+    if (lane.mode.size() != lane.members.size() || infos.size() != lane.members.size())
+        rc = MUCA_ERR_STATE;  // cannot happen: the round's arrays are sized at launch
     for (size_t i = 0; i < lane.members.size(); ++i) {
         Request* r = lane.members[i];
         if (rc != MUCA_OK || r->h->poisoned) {
-            retire(s, r, MUCA_ERR_DEVICE, std::string("round failed: ") + r->h->err);
+            retire(s, r, rc == MUCA_ERR_STATE ? rc : MUCA_ERR_DEVICE, std::string("round failed: ") + r->h->err);
             continue;
         }
         const muca_info& in = infos[i];
@@ -312,6 +316,11 @@ void lane_collect(muca_server* s, Lane& lane, const std::vector<muca_info>& info
 
 int lane_launch(muca_server* s, Lane& lane)
 {
+    if (!lane.joining.empty()) {
+        lane.members.insert(lane.members.end(), lane.joining.begin(), lane.joining.end());
+        lane.joining.clear();
+        lane.dirty = true;
+    }
     const size_t n = lane.members.size();
     if (n == 0)
         return MUCA_OK;
@@ -454,12 +463,15 @@ int muca_server_progress(muca_server* s, uint32_t* events)
     admit(s);
     for (auto& kv : s->lanes) {
         Lane& lane = kv.second;
-        if (lane.in_flight || lane.members.empty())
+        if (lane.in_flight || (lane.members.empty() && lane.joining.empty()))
             continue;
         if (int rc = lane_launch(s, lane)) {
             for (Request* r : lane.members)
                 retire(s, r, rc, s->err);
+            for (Request* r : lane.joining)
+                retire(s, r, rc, s->err);
             lane.members.clear();
+            lane.joining.clear();
             lane.dirty = true;
             return rc;
         }
@@ -511,7 +523,7 @@ int muca_server_stats(const muca_server* s, muca_server_counters* out)
     muca_server_counters o{};
     o.queued = (uint32_t)s->queue.size();
     for (const auto& kv : s->lanes)
-        o.active += (uint32_t)kv.second.members.size();
+        o.active += (uint32_t)(kv.second.members.size() + kv.second.joining.size());
     o.completed = s->completed;
     o.admitted = s->admitted;
     o.resident_bytes = s->arena.used();
