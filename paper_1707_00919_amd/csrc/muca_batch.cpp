@@ -428,8 +428,14 @@ int muca_batch_submit(muca_batch* b, const uint32_t* mode, const uint32_t* therm
         BATCH_HIP(b, hipEventRecord(b->ev_done, b->stream), "hipEventRecord");
         return MUCA_OK;
     }
-    // two-wave form while the batch leaves room for its producer waves
-    bool two_wave = active_blocks <= 2u * (uint32_t)b->cus;
+    // two-wave form while all of the batch's two-wave workgroups fit on the
+    // device at once, at most two per CU (LDS shares weighted by each L)
+    double lds_share = 0.0;
+    for (uint32_t i = 0; i < count; ++i)
+        if (form[i] == kFast && muca::split_sweep_supported(b->m[i]->L))
+            lds_share += (double)(b->m[i]->wpad / muca::kWave) *
+                         std::max(0.5, 1.0 / (double)(muca::kLdsPerCu / muca::split_lds_bytes(b->m[i]->L)));
+    bool two_wave = active_blocks <= 2u * (uint32_t)b->cus && lds_share <= (double)b->cus;
     if (b->flags & MUCA_BATCH_AUTOTUNE) {
         if (b->tuned_form >= 0)
             two_wave = b->tuned_form == 1;
@@ -465,8 +471,11 @@ int muca_batch_submit(muca_batch* b, const uint32_t* mode, const uint32_t* therm
         G.form = it->first.second;
         G.first_item = nitems;
         for (uint32_t i : mem) {
+            // a work item is one workgroup: 64 walkers, or for the one-wave form
+            // fast_waves_per_group(L) blocks of 64 that share one table
             const uint32_t blocks = b->m[i]->wpad / muca::kWave;
-            for (uint32_t blk = 0; blk < blocks; ++blk)
+            const uint32_t per = G.form == kFast ? muca::fast_waves_per_group(G.L) : 1u;
+            for (uint32_t blk = 0; blk < (blocks + per - 1) / per; ++blk)
                 items[nitems++] = muca::BatchItem{i, blk};
             key += std::to_string(i) + ":" + std::to_string(total[i]) + ",";
         }

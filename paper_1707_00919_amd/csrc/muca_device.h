@@ -73,11 +73,42 @@ struct InitArgs {
 inline uint32_t words_per_row(uint32_t L) { return (L + 31u) / 32u; }
 inline uint32_t padded_walkers(uint32_t walkers) { return (walkers + kWave - 1) / kWave * kWave; }
 
+// LDS an MI355X compute unit offers to the workgroups resident on it.
+constexpr uint32_t kLdsPerCu = 160u * 1024u;
+
+// LDS bytes of one workgroup of the fast sweep (a 28-byte record per energy
+// bin) and of the split sweep (the records plus a two-slot ring of Philox
+// words, one loop step of 64 walkers per slot).
+__host__ __device__ constexpr uint32_t fast_lds_bytes(uint32_t L) { return 28u * (L * L + 1u); }
+__host__ __device__ constexpr uint32_t split_lds_bytes(uint32_t L)
+{
+    return 28u * (L * L + 1u) + 2u * ((L % 4u == 0u ? 1u : 2u) * L / 4u) * (uint32_t)kWave * 16u;
+}
+
+// Waves (of 64 walkers each) per workgroup of the fast sweep.  The record
+// table is per workgroup; where it is so large that fewer than four
+// workgroups fit in a CU's LDS, several waves share one copy so that every
+// SIMD of the CU still gets a chain to run.
+__host__ __device__ constexpr uint32_t fast_waves_per_group(uint32_t L)
+{
+    return kLdsPerCu / fast_lds_bytes(L) >= 4u ? 1u : (kLdsPerCu / fast_lds_bytes(L) >= 2u ? 2u : 4u);
+}
+
+// The two-wave (split) form pays while every one of its workgroups is resident
+// at once and at most two share a CU (their producer waves then do not compete
+// with the chains); otherwise the one-wave form runs more chains at a time.
+inline bool prefer_split(uint32_t L, uint64_t blocks, uint32_t cus)
+{
+    const uint64_t per_cu = kLdsPerCu / split_lds_bytes(L);
+    return blocks <= (uint64_t)cus * (per_cu < 2u ? per_cu : 2u);
+}
+
 // Largest number of recorded sweeps one launch may run without a 32-bit LDS
-// histogram counter overflowing: 64 walkers * N attempts per sweep per bin.
+// histogram counter overflowing: every walker of a workgroup (up to
+// 64 * fast_waves_per_group(L)) adds N counts per sweep to the same table.
 inline uint32_t max_sweeps_per_launch(uint32_t L)
 {
-    const uint64_t per_sweep = (uint64_t)kWave * L * L;
+    const uint64_t per_sweep = (uint64_t)kWave * fast_waves_per_group(L) * L * L;
     const uint64_t m = 0xffffffffull / per_sweep;
     return m > 0x7fffffffull ? 0x7fffffffu : (uint32_t)m;
 }

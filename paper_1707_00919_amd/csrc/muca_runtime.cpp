@@ -434,10 +434,10 @@ int run_attempts(muca_instance* h, uint64_t therm, uint64_t recorded, bool updat
         (muca::split_sweep_supported(h->L) || muca::fast_sweep_supported(h->L)) &&
         fast_table(N, h->table5.data(), reinterpret_cast<uint32_t*>(h->h_table4))) {
         // The split kernel gives each 64 walkers a second wave for the random
-        // numbers; once more than two of its workgroups share a CU those waves
-        // compete with the chains for issue slots and the one-wave form wins.
+        // numbers; once its workgroups no longer all fit at once, or more than
+        // two share a CU, the one-wave form wins.
         const bool want_fast = (h->p.flags & MUCA_FLAG_FAST_KERNEL) != 0 ||
-                               (h->wpad / muca::kWave > 2u * (uint32_t)h->cus &&
+                               (!muca::prefer_split(h->L, h->wpad / muca::kWave, (uint32_t)h->cus) &&
                                 muca::fast_sweep_supported(h->L));
         if (muca::split_sweep_supported(h->L) && !(want_fast && muca::fast_sweep_supported(h->L)))
             variant = 2;

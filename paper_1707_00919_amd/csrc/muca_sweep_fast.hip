@@ -25,6 +25,8 @@
 //    hold); otherwise it runs the generic kernel with 64-bit thresholds.
 //  * The Philox block of the next four sites is computed while the current
 //    four attempts wait on LDS.
+//  * Where the record table is too large for four workgroups per CU (L >= 40)
+//    a workgroup holds two or four waves that share one table.
 #include "muca_device.h"
 
 #include <utility>
@@ -121,25 +123,13 @@ __device__ __forceinline__ void fast_row_step(RowBits<L>& st, uint32_t& z, Words
     }
 }
 
+// The chain of walker w (one lane) over all sweeps of the launch.
 template <int L>
-__device__ __forceinline__ void sweep_fast_kernel_body(const FastSweepArgs& a, uint32_t block)
+__device__ __forceinline__ void fast_chain(const FastSweepArgs& a, uint32_t w, uint8_t* lds)
 {
     using S = FastShape<L>;
     constexpr int N = S::N;
     constexpr int WPR = S::WPR;
-    __shared__ __attribute__((aligned(16))) uint8_t lds[S::LDS_BYTES];
-
-    const uint32_t lane = threadIdx.x;
-    const uint32_t w = block * kWave + lane;
-
-    // records: five thresholds S = T - 1 (by m), a zeroed histogram counter, pad
-    uint32_t* rec = reinterpret_cast<uint32_t*>(lds);
-    for (int i = lane; i < 7 * (N + 1); i += kWave) {
-        const int k = i / 7, j = i - 7 * (i / 7);
-        rec[i] = j < 5 ? a.table[k * 5 + j] : 0u;
-    }
-    __syncthreads();
-
     uint32_t* const mine = a.spins + w;
     const size_t stride = a.wpad;
     RowBits<L> st;
@@ -172,9 +162,35 @@ __device__ __forceinline__ void sweep_fast_kernel_body(const FastSweepArgs& a, u
         }
     }
     a.energy[w] = 4 * (int)((z - 8u) / 28u) - 2 * N;
+}
 
+// One workgroup: `group` covers the 64-walker blocks group * G .. group * G +
+// G - 1 (G = fast_waves_per_group(L)), one wave each, all sharing one record
+// table; waves past the instance's last block only help fill and drain it.
+template <int L>
+__device__ __forceinline__ void sweep_fast_kernel_body(const FastSweepArgs& a, uint32_t group)
+{
+    using S = FastShape<L>;
+    constexpr int N = S::N;
+    constexpr int G = (int)fast_waves_per_group(L);
+    static_assert(S::LDS_BYTES == (int)fast_lds_bytes(L), "LDS size formula");
+    __shared__ __attribute__((aligned(16))) uint8_t lds[S::LDS_BYTES];
+
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const uint32_t block = group * (uint32_t)G + threadIdx.x / kWave;
+    const uint32_t w = block * kWave + lane;
+
+    // records: five thresholds S = T - 1 (by m), a zeroed histogram counter, pad
+    uint32_t* rec = reinterpret_cast<uint32_t*>(lds);
+    for (int i = threadIdx.x; i < 7 * (N + 1); i += G * kWave) {
+        const int k = i / 7, j = i - 7 * (i / 7);
+        rec[i] = j < 5 ? a.table[k * 5 + j] : 0u;
+    }
     __syncthreads();
-    for (int k = lane; k <= N; k += kWave) {
+    if (w < a.wpad)
+        fast_chain<L>(a, w, lds);
+    __syncthreads();
+    for (int k = threadIdx.x; k <= N; k += G * kWave) {
         const uint32_t v = rec[7 * k + 5];
         if (v)
             atomicAdd(a.hist + k, (unsigned long long)v);
@@ -182,13 +198,14 @@ __device__ __forceinline__ void sweep_fast_kernel_body(const FastSweepArgs& a, u
 }
 
 template <int L>
-__global__ __launch_bounds__(64) void sweep_fast_kernel(FastSweepArgs a)
+__global__ __launch_bounds__(64 * fast_waves_per_group(L)) void sweep_fast_kernel(FastSweepArgs a)
 {
     sweep_fast_kernel_body<L>(a, blockIdx.x);
 }
 
 template <int L>
-__global__ __launch_bounds__(64) void sweep_fast_kernel_batch(const FastSweepArgs* args, const BatchItem* items)
+__global__ __launch_bounds__(64 * fast_waves_per_group(L)) void sweep_fast_kernel_batch(const FastSweepArgs* args,
+                                                                                       const BatchItem* items)
 {
     const BatchItem it = items[blockIdx.x];
     sweep_fast_kernel_body<L>(args[it.member], it.block);
@@ -197,14 +214,16 @@ __global__ __launch_bounds__(64) void sweep_fast_kernel_batch(const FastSweepArg
 template <int L>
 hipError_t launch_fast_L_batch_L(const FastSweepArgs* args, const BatchItem* items, uint32_t n, hipStream_t s)
 {
-    hipLaunchKernelGGL(sweep_fast_kernel_batch<L>, dim3(n), dim3(kWave), 0, s, args, items);
+    hipLaunchKernelGGL(sweep_fast_kernel_batch<L>, dim3(n), dim3(kWave * fast_waves_per_group(L)), 0, s, args,
+                       items);
     return hipGetLastError();
 }
 
 template <int L>
 hipError_t launch_fast_L(const FastSweepArgs& a, hipStream_t s)
 {
-    hipLaunchKernelGGL(sweep_fast_kernel<L>, dim3(a.wpad / kWave), dim3(kWave), 0, s, a);
+    constexpr uint32_t G = fast_waves_per_group(L);
+    hipLaunchKernelGGL(sweep_fast_kernel<L>, dim3((a.wpad / kWave + G - 1) / G), dim3(kWave * G), 0, s, a);
     return hipGetLastError();
 }
 

@@ -186,6 +186,7 @@ __device__ __forceinline__ void sweep_split_kernel_body(const FastSweepArgs& a, 
 {
     using S = SplitShape<L>;
     static_assert(S::LDS_BYTES <= 160 * 1024, "records and ring must fit in LDS");
+    static_assert(S::LDS_BYTES == (int)split_lds_bytes(L), "LDS size formula");
     constexpr int N = S::N;
     constexpr int WPR = S::WPR;
     __shared__ __attribute__((aligned(16))) uint8_t lds[S::LDS_BYTES];

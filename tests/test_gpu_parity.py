@@ -111,7 +111,8 @@ def test_small_workload_end_to_end():
 
 @pytest.mark.parametrize("L,W,seed", [(4, 64, 1), (6, 65, 2), (16, 257, 7), (30, 70, 9),
                                       (32, 4097, 11), (34, 66, 12), (48, 80, 13), (62, 65, 3),
-                                      (64, 64, 14)])
+                                      (64, 64, 14), (40, 200, 15), (44, 65, 16), (56, 130, 17),
+                                      (64, 320, 18), (48, 192, 19)])
 def test_kernel_variants_agree(L, W, seed):
     # split (two waves, thresholds fetched ahead), fast (one wave) and generic
     # (64-bit thresholds) sweep kernels: the same bits, and the oracle's
@@ -130,6 +131,23 @@ def test_kernel_variants_agree(L, W, seed):
         assert si["kernel_variant"] == variant
         assert_call(si, oi, s, o)
         assert_state(s, o)
+
+
+def test_many_walkers_at_large_L_use_wave_groups():
+    # more two-wave workgroups than fit on the device at once: the one-wave
+    # form runs, with four waves sharing one record table at L = 64
+    note("wave groups L=64 W=16448")
+    L, W, seed = 64, 16448, 20
+    s = Solver(L, W, seed)
+    o = oracle.OracleMuca(L, W, seed)
+    om = smooth_log_weights(L, seed)
+    s.set_log_weights(om)
+    o.set_log_weights(om)
+    si = s.iterate(1, 1)
+    oi = o.iterate(1, 1)
+    assert si["kernel_variant"] == 1
+    assert_call(si, oi, s, o)
+    assert_state(s, o)
 
 
 def test_zero_threshold_falls_back_to_generic_kernel():
