@@ -300,7 +300,7 @@ def bench_served(args):
     """Poisson request arrivals (muca_inputs.serving_requests) into the
     continuous-batching server; request latency percentiles and throughput."""
     import torch
-    from paper_1707_00919_amd import Server
+    from paper_1707_00919_amd import Server, Solver
     from muca_inputs import SERVE_REQUEST as Q, serving_requests
     reqs = serving_requests(duration=args.serve_duration)
     srv = Server(64 << 30, max_active_walkers=args.serve_max_walkers, batch_flags=1)
@@ -308,6 +308,7 @@ def bench_served(args):
     tickets = {}
     nxt = 0
     results = {}
+    lng_served = {}
     last_note = t0
     while len(results) < len(reqs):
         now = time.perf_counter() - t0
@@ -320,7 +321,10 @@ def bench_served(args):
         for t in list(tickets):
             r = srv.take(t)
             if r is not None:
-                results[tickets.pop(t)] = r[0]
+                i = tickets.pop(t)
+                results[i] = r[0]
+                if i < args.serve_solo_sample:
+                    lng_served[i] = r[1]
         if time.perf_counter() - last_note > 30.0:
             st = srv.stats()
             print("served %d/%d, active %d, queued %d, %.0f s" %
@@ -331,6 +335,22 @@ def bench_served(args):
     wall = time.perf_counter() - t0
     st = srv.stats()
     srv.close()
+    # one request per launch, in turn, for the first requests of the stream:
+    # the same solves alone (bit-identical results), timed back to back
+    solo = None
+    if args.serve_solo_sample:
+        t1 = time.perf_counter()
+        att_s, same = 0, True
+        for i in range(min(args.serve_solo_sample, len(reqs))):
+            _, L, W, sd = reqs[i]
+            a, _, lng = _solo_solve(Solver, L, W, sd, Q["iter_sweeps"], Q["min_flatness"],
+                                    Q["max_iterations"], Q["prod_therm"], Q["prod_sweeps"])
+            att_s += a
+            same &= bool(np.array_equal(lng.view(np.uint64), lng_served[i].view(np.uint64)))
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t1
+        solo = {"requests": min(args.serve_solo_sample, len(reqs)), "attempts_per_s": att_s / dt,
+                "wall_s": dt, "bit_identical_to_served": same}
     lat = [r["t_done"] - r["t_submit"] for r in results.values()]
     ttcw = [r["t_weights"] - r["t_submit"] for r in results.values()]
     att = sum(r["attempts"] for r in results.values())
@@ -349,6 +369,8 @@ def bench_served(args):
         "converged": sum(1 for r in results.values() if r["status"] == 0),
         "failed": sum(1 for r in results.values() if r["status"] not in (0, 5)),
         "makespan_s": wall, "peak_counters": st,
+        "one_per_launch_sample": solo,
+        "speedup_vs_one_per_launch": (att / wall) / solo["attempts_per_s"] if solo else None,
     }
     print(json.dumps(out), flush=True)
 
@@ -416,6 +438,9 @@ def main():
                          "and paper-schedule workloads, each with its own JSON line")
     ap.add_argument("--serve-duration", type=float, default=60.0)
     ap.add_argument("--serve-max-walkers", type=int, default=1 << 17)
+    ap.add_argument("--serve-solo-sample", type=int, default=24,
+                    help="solve this many of the first requests alone, one per launch, "
+                         "for the comparison rate")
     ap.add_argument("--profile-pass", action="store_true",
                     help="short sweep + calibration copy for rocprofv3 counter runs")
     args = ap.parse_args()

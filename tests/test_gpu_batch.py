@@ -194,3 +194,33 @@ def test_changing_membership():
             assert infos[k]["sweep_counter"] == si["sweep_counter"]
     for a, c in zip(solo, pool):
         same(a, c)
+
+
+def test_batched_workload_full_size_sampled_walkers():
+    # the 48 instances of the batched workload at their full sizes, in the
+    # launch form the benchmark uses (graph + autotune, two rounds so that
+    # both kernel forms run): sampled walkers of every instance against the
+    # oracle run on just those walkers
+    from paper_1707_00919_amd import Batch, Solver, _abi
+    from muca_inputs import batch_instances
+    note("batched workload, full size, sampled walkers")
+    inst = batch_instances()
+    members = [Solver(L, W, sd) for L, W, sd in inst]
+    oms = [smooth_log_weights(L, sd + 7) for L, _, sd in inst]
+    for m, om in zip(members, oms):
+        m.set_log_weights(om)
+    b = Batch(members, flags=_abi.MUCA_BATCH_GRAPH | _abi.MUCA_BATCH_AUTOTUNE)
+    forms = set()
+    for _ in range(2):
+        infos = b.run([2] * len(members), 1, 1)
+        forms |= {i["kernel_variant"] for i in infos}
+    assert forms == {1, 2}
+    rng = np.random.default_rng(5)
+    for (L, W, sd), m, om in zip(inst, members, oms):
+        ids = np.unique(np.concatenate([[0, W - 1], rng.integers(0, W, 6)])).astype(np.uint32)
+        o = oracle.OracleMuca(L, W, sd, walker_ids=ids)
+        o.set_log_weights(om)
+        o.production(1, 1)
+        o.production(1, 1)
+        np.testing.assert_array_equal(m.energies()[ids], o.energies)
+        np.testing.assert_array_equal(m.spins()[ids], o.spins)
