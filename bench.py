@@ -423,6 +423,75 @@ def bench_schedule(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_production(args):
+    """Production analysis at L = 32 (Sec. 3.3): at the exact weights, a
+    production run of 16384 walkers in 100 blocks, jackknife errors of ln g,
+    <E>/N and C/N at three temperatures against their exact values, and the
+    paper's statistical gain: squared jackknife errors of the oracle on the
+    host cores (24 walkers, as the paper's CPU node) over those of the GPU,
+    scaled to equal run time."""
+    import torch
+    from paper_1707_00919_amd import Solver, analysis
+    import oracle
+    from oracle import analysis as oracle_analysis
+    L, W, blocks = 32, 16384, 100
+    ln_g = exact_ln_g(L)
+    omega = np.where(np.isfinite(ln_g), -ln_g, 0.0)
+    betas = [0.3, 0.4406867935, 0.6]
+    s = Solver(L, W, 1)
+    s.set_log_weights(omega)
+    s.production(10000, 0)   # the walkers start from random spins (reading 8)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    h = analysis.production_blocks(s, 0, args.block_sweeps, blocks)
+    t_gpu = time.perf_counter() - t0
+    s.close()
+    est, err = analysis.jackknife_log_dos(L, h, omega, 1)
+    e, ee, c, ce = analysis.canonical(L, h, omega, betas)
+    ex, cx = oracle_analysis.canonical(ln_g, betas)
+    m = np.isfinite(ln_g)
+    dev = np.abs(est[m] - ln_g[m])
+    # the oracle: 24 walkers on the host cores, same weights, bounded time
+    o = oracle.OracleMuca(L, 24, 1)
+    o.set_log_weights(omega)
+    o.production(10000, 0)
+    tw = time.perf_counter()
+    o.production(0, 100)
+    rate = 24 * L * L * 100 / (time.perf_counter() - tw)
+    t1 = time.perf_counter()
+    hc = []
+    per_block = max(1, int(args.cpu_seconds * rate / (24 * L * L * blocks)))
+    for _ in range(blocks):
+        o.production(0, per_block)
+        hc.append(o.hist.copy())
+    t_cpu = time.perf_counter() - t1
+    est_c, err_c = oracle_analysis.jackknife_log_dos(np.array(hc), omega, 1)
+    both = m & np.isfinite(err) & np.isfinite(err_c) & (err > 0) & (err_c > 0)
+    gain = float(np.mean((err_c[both] ** 2 * t_cpu) / (err[both] ** 2 * t_gpu)))
+    out = {
+        "metric": "production analysis at L=32: jackknife errors, canonical averages, "
+                  "statistical gain over the CPU oracle at equal time",
+        "value": gain, "unit": "x (eps_cpu^2 / eps_gpu^2 at equal run time)", "n_gpus": 1,
+        "steps": 1, "warmup": 0, "ms_per_step": t_gpu * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": "production_L32", "L": L, "walkers": W, "blocks": blocks,
+                   "block_sweeps": args.block_sweeps, "weights": "exact, omega = -ln g",
+                   "cpu": "oracle, 24 walkers, %d sweeps per block" % per_block},
+        "gpu_production_s": t_gpu, "gpu_attempts_per_s": W * L * L * blocks * args.block_sweeps / t_gpu,
+        "cpu_production_s": t_cpu,
+        "ln_g_max_abs_dev": float(dev.max()),
+        "ln_g_jackknife_err_mean": float(np.mean(err[m & np.isfinite(err)])),
+        "ln_g_frac_within_2_err": float(np.mean(dev < 2 * err[m])),
+        "betas": betas,
+        "energy_per_spin": list(map(float, e)), "energy_err": list(map(float, ee)),
+        "energy_exact": list(map(float, ex)),
+        "specific_heat_per_spin": list(map(float, c)), "specific_heat_err": list(map(float, ce)),
+        "specific_heat_exact": list(map(float, cx)),
+        "cpu_cores": int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count(),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -433,10 +502,13 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-hardware-rate", action="store_true")
     ap.add_argument("--workload", default=WORKLOAD,
-                    choices=[WORKLOAD, "batched48", "served_poisson20", "paper_schedule_L32"],
+                    choices=[WORKLOAD, "batched48", "served_poisson20", "paper_schedule_L32",
+                             "production_L32"],
                     help="the headline workload (default) or one of the batched, served "
                          "and paper-schedule workloads, each with its own JSON line")
     ap.add_argument("--serve-duration", type=float, default=60.0)
+    ap.add_argument("--block-sweeps", type=int, default=1000)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--serve-max-walkers", type=int, default=1 << 17)
     ap.add_argument("--serve-solo-sample", type=int, default=24,
                     help="solve this many of the first requests alone, one per launch, "
@@ -462,6 +534,8 @@ def main():
         return bench_served(args)
     if args.workload == "paper_schedule_L32":
         return bench_schedule(args)
+    if args.workload == "production_L32":
+        return bench_production(args)
     wl = WORKLOADS[WORKLOAD]
     ln_g = exact_ln_g(wl["L"])
     if args.profile_pass:
