@@ -61,7 +61,7 @@ __device__ __forceinline__ uint32_t lds_load(const uint8_t* lds, uint32_t byte)
 }
 
 template <int L, int P>
-__device__ __forceinline__ void fast_attempt(RowBits<L>& rb, uint32_t& z, Words4& rcur,
+__device__ __forceinline__ void fast_attempt(RowBits<L>& rb, uint32_t& z, uint32_t& inc_last, Words4& rcur,
                                              Words4& rnext, const FastCtx& c, uint8_t* lds)
 {
     using S = FastShape<L>;
@@ -75,6 +75,9 @@ __device__ __forceinline__ void fast_attempt(RowBits<L>& rb, uint32_t& z, Words4
     // ms = (anti-aligned neighbours) - 2 = -(change of the energy bin)
     const int ms = bond_count<L, X>(rb.nb, vert_minus_two<L, X>(rb));
     const uint32_t thr = lds_load(lds, z + (uint32_t)(ms * 4));
+    // the bin the previous attempt left the walker in, counted after the load
+    // so that the load does not wait behind this read-modify-write
+    atomicAdd(reinterpret_cast<uint32_t*>(lds + z + 12), X == 0 ? inc_last : c.inc);
     const uint32_t target = z - (uint32_t)(ms * 28);
     const bool accept = r <= thr;
     z = accept ? target : z;
@@ -88,19 +91,20 @@ __device__ __forceinline__ void fast_attempt(RowBits<L>& rb, uint32_t& z, Words4
         rb.nb[w] = accept ? nbf[w] : rb.nb[w];
     if constexpr (X == 0)
         rb.f0 = accept ? 1u : 0u;
-    atomicAdd(reinterpret_cast<uint32_t*>(lds + z + 12), c.inc);
+    if constexpr (X + 1 == L)
+        inc_last = c.inc;
 }
 
 template <int L, int RR, int... Xs>
-__device__ __forceinline__ void fast_row_sites(RowBits<L>& st, uint32_t& z, Words4& rcur,
+__device__ __forceinline__ void fast_row_sites(RowBits<L>& st, uint32_t& z, uint32_t& inc_last, Words4& rcur,
                                                Words4& rnext, const FastCtx& c, uint8_t* lds,
                                                std::integer_sequence<int, Xs...>)
 {
-    (fast_attempt<L, RR * L + Xs>(st, z, rcur, rnext, c, lds), ...);
+    (fast_attempt<L, RR * L + Xs>(st, z, inc_last, rcur, rnext, c, lds), ...);
 }
 
 template <int L, int RR>
-__device__ __forceinline__ void fast_row_step(RowBits<L>& st, uint32_t& z, Words4& rcur,
+__device__ __forceinline__ void fast_row_step(RowBits<L>& st, uint32_t& z, uint32_t& inc_last, Words4& rcur,
                                               Words4& rnext, const FastCtx& c, uint8_t* lds,
                                               uint32_t* mine, size_t stride, int y)
 {
@@ -112,7 +116,7 @@ __device__ __forceinline__ void fast_row_step(RowBits<L>& st, uint32_t& z, Words
     for (int j = 0; j < WPR; ++j)
         nx[j] = mine[(size_t)(ynext * WPR + j) * stride];
     rowbits_begin<L>(st);
-    fast_row_sites<L, RR>(st, z, rcur, rnext, c, lds, std::make_integer_sequence<int, L>{});
+    fast_row_sites<L, RR>(st, z, inc_last, rcur, rnext, c, lds, std::make_integer_sequence<int, L>{});
     rowbits_end<L>(st);
 #pragma unroll
     for (int j = 0; j < WPR; ++j) {
@@ -142,6 +146,7 @@ __device__ __forceinline__ void fast_chain(const FastSweepArgs& a, uint32_t w, u
     st.f0 = 0u;
     const int k0 = (a.energy[w] + 2 * N) >> 2;
     uint32_t z = 28u * (uint32_t)k0 + 8u;
+    uint32_t inc_last = 0u;  // no attempt yet
     const uint32_t live = w < a.walkers ? 1u : 0u;
 
     FastCtx c;
@@ -156,11 +161,12 @@ __device__ __forceinline__ void fast_chain(const FastSweepArgs& a, uint32_t w, u
             c.blk0 = (uint32_t)(y * L) >> 2;
             Words4 rcur;
             Words4 rnext = philox10(c.blk0, c.c1, c.c2, 0u, c.seed, c.walker);
-            fast_row_step<L, 0>(st, z, rcur, rnext, c, lds, mine, stride, y);
+            fast_row_step<L, 0>(st, z, inc_last, rcur, rnext, c, lds, mine, stride, y);
             if constexpr (S::RPS == 2)
-                fast_row_step<L, 1>(st, z, rcur, rnext, c, lds, mine, stride, y);
+                fast_row_step<L, 1>(st, z, inc_last, rcur, rnext, c, lds, mine, stride, y);
         }
     }
+    atomicAdd(reinterpret_cast<uint32_t*>(lds + z + 12), inc_last);  // the last attempt
     a.energy[w] = 4 * (int)((z - 8u) / 28u) - 2 * N;
 }
 

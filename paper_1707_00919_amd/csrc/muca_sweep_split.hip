@@ -54,6 +54,7 @@ struct ChainState {
     uint32_t thr_keep;   // threshold S of the next site if the previous site
     uint32_t thr_flip;   // was kept / flipped (loads may still be in flight)
     bool prev_flip;      // the previous site flipped
+    uint32_t inc_last;   // record flag of the attempt that left the walker in z
 };
 
 __device__ __forceinline__ uint32_t lds_u32(const uint8_t* lds, uint32_t byte)
@@ -111,6 +112,10 @@ __device__ __forceinline__ void chain_attempt(ChainState<L>& st, Words4& rc, Wor
         next_keep = lds_u32(lds, st.z + (uint32_t)(ms_keep * 4));
         next_flip = lds_u32(lds, zf + (uint32_t)(ms_flip * 4));
     }
+    // the bin the previous attempt left the walker in is counted here, after
+    // the loads above: LDS answers a wave in order, so the loads do not wait
+    // behind this read-modify-write
+    atomicAdd(reinterpret_cast<uint32_t*>(lds + st.z + 12), X == 0 ? st.inc_last : inc);
     __builtin_amdgcn_sched_barrier(0);
     const uint32_t thr = st.prev_flip ? st.thr_flip : st.thr_keep;
     const bool accept = r <= thr;
@@ -120,7 +125,8 @@ __device__ __forceinline__ void chain_attempt(ChainState<L>& st, Words4& rc, Wor
         st.rb.nb[w] = accept ? nbf[w] : st.rb.nb[w];
     if constexpr (X == 0)
         st.rb.f0 = accept ? 1u : 0u;
-    atomicAdd(reinterpret_cast<uint32_t*>(lds + st.z + 12), inc);
+    if constexpr (X + 1 == L)
+        st.inc_last = inc;
     if constexpr (X + 1 < L) {
         st.ms = accept ? ms_flip : ms_keep;
         st.thr_keep = next_keep;
@@ -218,6 +224,7 @@ __device__ __forceinline__ void sweep_split_kernel_body(const FastSweepArgs& a, 
         }
         st.rb.f0 = 0u;
         st.z = 28u * (uint32_t)((a.energy[w] + 2 * N) >> 2) + 8u;
+        st.inc_last = 0u;  // no attempt yet
     }
 
     for (uint32_t s = 0; s < steps; ++s) {
@@ -237,8 +244,10 @@ __device__ __forceinline__ void sweep_split_kernel_body(const FastSweepArgs& a, 
         }
         __syncthreads();
     }
-    if (consumer)
+    if (consumer) {
+        atomicAdd(reinterpret_cast<uint32_t*>(lds + st.z + 12), st.inc_last);  // the last attempt
         a.energy[w] = 4 * (int)((st.z - 8u) / 28u) - 2 * N;
+    }
 
     __syncthreads();
     for (int k = threadIdx.x; k <= N; k += 2 * kWave) {
