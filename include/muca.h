@@ -25,8 +25,10 @@
  *   computed on the host in IEEE double once per call (T = 0 where k' is
  *   outside 0..N).  T lies in [0, 2^32], so it is stored as uint64.
  *   After every recorded attempt the current energy bin is counted.
- *   Every sweep (thermalisation or recorded) advances the instance's sweep
- *   counter by one; it is never reset.
+ *   The instance keeps its position p, the attempts made per walker so far:
+ *   attempt p is made at site i = p mod N of sweep t = p div N.  Every
+ *   attempt (thermalisation or recorded) advances p by one; it is never
+ *   reset.  Calls counted in sweeps move p by N per sweep.
  *
  * Ownership: the library owns the instance and, unless the caller passes a
  * device workspace, all device memory.  Host arrays passed in are read or
@@ -258,8 +260,9 @@ int muca_canonical(uint32_t L, uint32_t blocks, const uint64_t* block_hists, con
  * own weights and histogram); every instance's results are bit-identical to
  * running it alone.  One round runs, for every member, either a weight
  * iteration, a production call or nothing; the members' sweeps are grouped by
- * (L, kernel form) and each group is one launch whose workgroups each take 64
- * walkers of one member; the groups run concurrently.
+ * (L, kernel form) and each group is one launch whose workgroups each take
+ * walkers of one member (64, or 128 / 256 sharing one threshold table for
+ * the one-wave form at L >= 40); the groups run concurrently.
  * ------------------------------------------------------------------------ */
 typedef struct muca_batch muca_batch;
 
