@@ -1,0 +1,212 @@
+// muca_chain.h -- the per-walker Metropolis chain of one row, shared by the
+// one-wave (fast) and two-wave (split) sweep kernels (L <= 64).
+//
+// One lane runs one walker; all lanes of a wave are on the same site
+// (typewriter order, Sec. 2.3).  The walker's energy bin k is kept as the byte
+// address z = 28k + 8 of its 28-byte LDS record (five thresholds S = T - 1
+// by the number m of anti-aligned neighbours, the bin's histogram counter, a
+// pad word): the threshold of a move with m anti-aligned neighbours is at
+// z + 4(m - 2), the target bin's record at z - 28(m - 2), the counter at z + 12.
+//
+// Each walker's chain is serial (the energy after one attempt picks the next
+// threshold), so a chain step's latency sets the pace.  The step hides the
+// LDS round trip of the threshold: while attempt x is being decided, the two
+// thresholds attempt x+1 can need -- site x kept, or site x flipped (which
+// moves the bin and the left-neighbour bond of site x+1) -- are already
+// loading; after the compare the step picks one.  The bin an attempt leaves
+// the walker in is counted one attempt later, after the next loads are
+// issued, since LDS answers a wave's requests in order.
+//
+// The random words come from a Draws source: first() returns the four Philox
+// words of block 0 of the current loop step, and advance<B, PART>(rn), called
+// at the attempts with P & 3 = PART = 0..3 of the block before B, delivers
+// block B into rn by the last of those calls (an LDS ring filled by a producer
+// wave does it in one load; Philox computed in place spreads its ten rounds
+// over the four attempts, so that they fill the chain's dependency stalls).
+#pragma once
+
+#include <utility>
+
+#include "muca_device.h"
+#include "muca_rowbits.h"
+#include "philox.h"
+
+namespace muca {
+
+template <int L>
+struct ChainShape {
+    static constexpr int N = L * L;
+    static constexpr int WPR = (L + 31) / 32;
+    static constexpr int RPS = (L % 4 == 0) ? 1 : 2;  // rows per loop step: whole Philox blocks
+    static constexpr int STEPS = L / RPS;             // loop steps per sweep
+    static constexpr int BLOCKS = RPS * L / 4;        // Philox blocks per loop step
+    static constexpr int REC = 28;                    // LDS bytes per energy bin
+    static constexpr int REC_BYTES = REC * (N + 1);
+};
+
+template <int L>
+struct ChainState {
+    RowBits<L> rb;
+    uint32_t z;          // byte address of the record of the current bin + 8
+    int ms;              // (anti-aligned neighbours of the next site) - 2
+    uint32_t thr_keep;   // threshold S of the next site if the previous site
+    uint32_t thr_flip;   // was kept / flipped (loads may still be in flight)
+    bool prev_flip;      // the previous site flipped
+    uint32_t inc_last;   // record flag of the attempt that left the walker in z
+};
+
+__device__ __forceinline__ uint32_t lds_u32(const uint8_t* lds, uint32_t byte)
+{
+    return *reinterpret_cast<const uint32_t*>(lds + byte);
+}
+
+// Fills the records: five thresholds S = T - 1 (by m) from table[k*5 + m], a
+// zeroed counter, a pad word.  All threads of the workgroup take part.
+template <int L>
+__device__ __forceinline__ void chain_records_fill(uint8_t* lds, const uint32_t* table, int first, int stride)
+{
+    constexpr int N = L * L;
+    uint32_t* rec = reinterpret_cast<uint32_t*>(lds);
+    for (int i = first; i < 7 * (N + 1); i += stride) {
+        const int k = i / 7, j = i - 7 * (i / 7);
+        rec[i] = j < 5 ? table[k * 5 + j] : 0u;
+    }
+}
+
+// Adds the records' counters into the instance histogram (one atomic pass).
+template <int L>
+__device__ __forceinline__ void chain_records_flush(const uint8_t* lds, unsigned long long* hist, int first,
+                                                    int stride)
+{
+    constexpr int N = L * L;
+    const uint32_t* rec = reinterpret_cast<const uint32_t*>(lds);
+    for (int k = first; k <= N; k += stride) {
+        const uint32_t v = rec[7 * k + 5];
+        if (v)
+            atomicAdd(hist + k, (unsigned long long)v);
+    }
+}
+
+// Walker state from its lattice and energy; no attempt counted yet.
+template <int L>
+__device__ __forceinline__ void chain_load(ChainState<L>& st, const uint32_t* mine, size_t stride, int32_t energy)
+{
+    constexpr int WPR = ChainShape<L>::WPR;
+#pragma unroll
+    for (int j = 0; j < WPR; ++j) {
+        st.rb.up[j] = mine[(size_t)((L - 1) * WPR + j) * stride];
+        st.rb.cur[j] = mine[(size_t)j * stride];
+        st.rb.dn[j] = mine[(size_t)(WPR + j) * stride];
+    }
+    st.rb.f0 = 0u;
+    st.z = 28u * (uint32_t)((energy + 2 * L * L) >> 2) + 8u;
+    st.inc_last = 0u;
+}
+
+// Counts the bin of the launch's last attempt; returns the walker's energy.
+template <int L>
+__device__ __forceinline__ int32_t chain_finish(ChainState<L>& st, uint8_t* lds)
+{
+    atomicAdd(reinterpret_cast<uint32_t*>(lds + st.z + 12), st.inc_last);
+    return 4 * (int32_t)((st.z - 8u) / 28u) - 2 * L * L;
+}
+
+template <int L>
+__device__ __forceinline__ void chain_row_begin(ChainState<L>& st, const uint8_t* lds)
+{
+    rowbits_begin<L>(st.rb);
+    st.ms = bond_count<L, 0>(st.rb.nb, vert_minus_two<L, 0>(st.rb));
+    st.thr_keep = lds_u32(lds, st.z + (uint32_t)(st.ms * 4));
+    st.thr_flip = st.thr_keep;
+    st.prev_flip = false;
+}
+
+// Attempt at site X = P % L; P counts the sites of the loop step.
+//
+// Order inside one attempt: first the two threshold loads that site X+1 may
+// need (they depend only on the state after site X-1) and the count of the
+// previous attempt's bin, then the threshold of site X is picked from the pair
+// loaded one attempt earlier, compared, and the state updated.  The scheduling
+// barrier keeps the compiler from moving that pick, and the wait on LDS it
+// implies, above the new loads: each load then has a whole attempt of
+// independent work to hide behind.
+template <int L, int P, class Draws>
+__device__ __forceinline__ void chain_attempt(ChainState<L>& st, Words4& rc, Words4& rn, Draws& draws,
+                                              uint8_t* lds, uint32_t inc)
+{
+    using S = ChainShape<L>;
+    constexpr int X = P % L;
+    if constexpr ((P & 3) == 0)
+        rc = rn;
+    if constexpr ((P >> 2) + 1 < S::BLOCKS)
+        draws.template advance<(P >> 2) + 1, (P & 3)>(rn);
+    const uint32_t r = rc.w[P & 3];
+    uint32_t nbf[S::WPR];
+#pragma unroll
+    for (int w = 0; w < S::WPR; ++w)
+        nbf[w] = st.rb.nb[w];
+    bond_flip<L, X>(nbf);
+    const uint32_t zf = st.z - (uint32_t)(st.ms * 28);
+    int ms_keep = 0, ms_flip = 0;
+    uint32_t next_keep = 0u, next_flip = 0u;
+    if constexpr (X + 1 < L) {
+        // both possible thresholds of site X+1
+        const int v1 = vert_minus_two<L, X + 1>(st.rb);
+        ms_keep = bond_count<L, X + 1>(st.rb.nb, v1);
+        ms_flip = bond_count<L, X + 1>(nbf, v1);
+        next_keep = lds_u32(lds, st.z + (uint32_t)(ms_keep * 4));
+        next_flip = lds_u32(lds, zf + (uint32_t)(ms_flip * 4));
+    }
+    atomicAdd(reinterpret_cast<uint32_t*>(lds + st.z + 12), X == 0 ? st.inc_last : inc);
+    __builtin_amdgcn_sched_barrier(0);
+    const uint32_t thr = st.prev_flip ? st.thr_flip : st.thr_keep;
+    const bool accept = r <= thr;
+    st.z = accept ? zf : st.z;
+#pragma unroll
+    for (int w = 0; w < S::WPR; ++w)
+        st.rb.nb[w] = accept ? nbf[w] : st.rb.nb[w];
+    if constexpr (X == 0)
+        st.rb.f0 = accept ? 1u : 0u;
+    if constexpr (X + 1 == L)
+        st.inc_last = inc;
+    if constexpr (X + 1 < L) {
+        st.ms = accept ? ms_flip : ms_keep;
+        st.thr_keep = next_keep;
+        st.thr_flip = next_flip;
+        st.prev_flip = accept;
+    }
+}
+
+template <int L, int RR, class Draws, int... Xs>
+__device__ __forceinline__ void chain_row_sites(ChainState<L>& st, Words4& rc, Words4& rn, Draws& draws,
+                                                uint8_t* lds, uint32_t inc, std::integer_sequence<int, Xs...>)
+{
+    (chain_attempt<L, RR * L + Xs>(st, rc, rn, draws, lds, inc), ...);
+}
+
+// Row RR of a loop step that starts at row y: prefetch row y+RR+2, run the
+// row's L attempts, write the row back and slide the window down by one.
+template <int L, int RR, class Draws>
+__device__ __forceinline__ void chain_row(ChainState<L>& st, Words4& rc, Words4& rn, Draws& draws,
+                                          uint8_t* lds, uint32_t inc, uint32_t* mine, size_t stride, int y)
+{
+    constexpr int WPR = ChainShape<L>::WPR;
+    const int yy = y + RR;
+    const int ynext = (yy + 2) % L;
+    uint32_t nx[WPR];
+#pragma unroll
+    for (int j = 0; j < WPR; ++j)
+        nx[j] = mine[(size_t)(ynext * WPR + j) * stride];
+    chain_row_begin<L>(st, lds);
+    chain_row_sites<L, RR>(st, rc, rn, draws, lds, inc, std::make_integer_sequence<int, L>{});
+    rowbits_end<L>(st.rb);
+#pragma unroll
+    for (int j = 0; j < WPR; ++j) {
+        mine[(size_t)(yy * WPR + j) * stride] = st.rb.cur[j];
+        st.rb.up[j] = st.rb.cur[j];
+        st.rb.cur[j] = st.rb.dn[j];
+        st.rb.dn[j] = nx[j];
+    }
+}
+
+}  // namespace muca

@@ -26,29 +26,42 @@ struct Words4 {
 // of the second are scalar work.  From the third round on every word differs
 // per lane; there the two three-input XORs of a round are single gfx950
 // v_bitop3_b32 instructions (truth table 0x96 = a ^ b ^ c).
+struct PhiloxState {
+    uint32_t c0, c1, c2, c3;  // counter, becoming the output
+    uint32_t k0, k1;          // key of the next round
+};
+
+// Rounds R0 .. R1-1 of a block started with key (k0, k1) at round 0.
+template <int R0, int R1>
+__device__ __forceinline__ void philox_rounds(PhiloxState& s)
+{
+#pragma unroll
+    for (int round = R0; round < R1; ++round) {
+        const uint64_t pa = (uint64_t)kPhiloxMulA * s.c0;
+        const uint64_t pb = (uint64_t)kPhiloxMulB * s.c2;
+        uint32_t n0, n2;
+        if (round < 2) {
+            n0 = (uint32_t)(pb >> 32) ^ s.c1 ^ s.k0;
+            n2 = (uint32_t)(pa >> 32) ^ s.c3 ^ s.k1;
+        } else {
+            n0 = __builtin_amdgcn_bitop3_b32((uint32_t)(pb >> 32), s.c1, s.k0, 0x96);
+            n2 = __builtin_amdgcn_bitop3_b32((uint32_t)(pa >> 32), s.c3, s.k1, 0x96);
+        }
+        s.c1 = (uint32_t)pb;
+        s.c3 = (uint32_t)pa;
+        s.c0 = n0;
+        s.c2 = n2;
+        s.k0 += kPhiloxWeylA;
+        s.k1 += kPhiloxWeylB;
+    }
+}
+
 __device__ __forceinline__ Words4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                            uint32_t k0, uint32_t k1)
 {
-#pragma unroll
-    for (int round = 0; round < 10; ++round) {
-        const uint64_t pa = (uint64_t)kPhiloxMulA * c0;
-        const uint64_t pb = (uint64_t)kPhiloxMulB * c2;
-        uint32_t n0, n2;
-        if (round < 2) {
-            n0 = (uint32_t)(pb >> 32) ^ c1 ^ k0;
-            n2 = (uint32_t)(pa >> 32) ^ c3 ^ k1;
-        } else {
-            n0 = __builtin_amdgcn_bitop3_b32((uint32_t)(pb >> 32), c1, k0, 0x96);
-            n2 = __builtin_amdgcn_bitop3_b32((uint32_t)(pa >> 32), c3, k1, 0x96);
-        }
-        c1 = (uint32_t)pb;
-        c3 = (uint32_t)pa;
-        c0 = n0;
-        c2 = n2;
-        k0 += kPhiloxWeylA;
-        k1 += kPhiloxWeylB;
-    }
-    return Words4{{c0, c1, c2, c3}};
+    PhiloxState s{c0, c1, c2, c3, k0, k1};
+    philox_rounds<0, 10>(s);
+    return Words4{{s.c0, s.c1, s.c2, s.c3}};
 }
 
 }  // namespace muca
