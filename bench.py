@@ -498,7 +498,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--iter-cap", type=int, default=2000)
-    ap.add_argument("--cpu-sweeps", type=int, default=40)
+    ap.add_argument("--cpu-sweeps", type=int, default=400)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-hardware-rate", action="store_true")
     ap.add_argument("--workload", default=WORKLOAD,
