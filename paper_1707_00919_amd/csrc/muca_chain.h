@@ -150,10 +150,25 @@ __device__ __forceinline__ void chain_attempt(ChainState<L>& st, Words4& rc, Wor
     int ms_keep = 0, ms_flip = 0;
     uint32_t next_keep = 0u, next_flip = 0u;
     if constexpr (X + 1 < L) {
-        // both possible thresholds of site X+1
+        // both possible thresholds of site X+1.  Its bonds are X (to site X,
+        // changed only if site X flips now) and X+1 (to site X+2, not yet
+        // visited in this row -- or, for the last site, to site 0, which
+        // flipped iff f0): both follow from the row-start bond word, so the
+        // counts do not wait for the previous compare.
+        uint32_t nbk[S::WPR];
+#pragma unroll
+        for (int w = 0; w < S::WPR; ++w)
+            nbk[w] = st.rb.nb0[w];
+        if constexpr (X + 2 == L)
+            nbk[(L - 1) >> 5] ^= st.rb.f0 << ((L - 1) & 31);
+        uint32_t nbkf[S::WPR];
+#pragma unroll
+        for (int w = 0; w < S::WPR; ++w)
+            nbkf[w] = nbk[w];
+        bond_flip<L, X>(nbkf);
         const int v1 = vert_minus_two<L, X + 1>(st.rb);
-        ms_keep = bond_count<L, X + 1>(st.rb.nb, v1);
-        ms_flip = bond_count<L, X + 1>(nbf, v1);
+        ms_keep = bond_count<L, X + 1>(nbk, v1);
+        ms_flip = bond_count<L, X + 1>(nbkf, v1);
         next_keep = lds_u32(lds, st.z + (uint32_t)(ms_keep * 4));
         next_flip = lds_u32(lds, zf + (uint32_t)(ms_flip * 4));
     }
