@@ -80,6 +80,12 @@ struct muca_batch {
     std::vector<uint32_t> mode, therm, sweeps, form;
     std::vector<uint64_t> total;
     uint32_t launches = 0;
+    // with MUCA_BATCH_GRAPH the host half of a round runs inside the graph, as
+    // a host node after the histogram download; its results wait here
+    bool host_in_graph = false;
+    std::vector<muca_info> round_infos;
+    int host_rc = MUCA_OK;
+    std::string host_err;
     // autotuner: attempts/ms of the two-wave and one-wave forms
     uint32_t round = 0;
     double tuned_rate[2] = {0.0, 0.0};
@@ -192,6 +198,36 @@ int enqueue_round(muca_batch* b, size_t stage_used, const std::vector<Group>& gr
         BATCH_HIP(b, hipStreamWaitEvent(b->stream, b->gevents[g], 0), "hipStreamWaitEvent");
     }
     return MUCA_OK;
+}
+
+// The host half of a round for every member that ran: histogram into the
+// member, the same finish as a single call (sum check, statistics, Eq. 4).
+int finish_members(muca_batch* b, double ms, std::vector<muca_info>& out, std::string* err)
+{
+    int result = MUCA_OK;
+    out.assign(b->m.size(), muca_info{});
+    for (size_t i = 0; i < b->m.size(); ++i) {
+        if (b->mode[i] == MUCA_BATCH_SKIP)
+            continue;
+        muca_instance* h = b->m[i];
+        std::memcpy(h->hist.data(), b->h_hist + b->hist_off[i], ((size_t)h->N + 1) * sizeof(uint64_t));
+        const int rc = finish_call(h, (uint64_t)b->therm[i] * h->N, (uint64_t)b->sweeps[i] * h->N,
+                                   b->mode[i] == MUCA_BATCH_ITERATE, ms, b->launches, b->form[i], &out[i]);
+        if (rc != MUCA_OK && result == MUCA_OK) {
+            result = rc;
+            *err = "member " + std::to_string(i) + ": " + h->err;
+        }
+    }
+    return result;
+}
+
+// Host node of a captured round.  It runs on a runtime thread once the
+// histograms are on the host; it calls no HIP function.
+void host_finish_node(void* arg)
+{
+    muca_batch* b = static_cast<muca_batch*>(arg);
+    b->host_err.clear();
+    b->host_rc = finish_members(b, 0.0, b->round_infos, &b->host_err);
 }
 
 }  // namespace
@@ -498,6 +534,63 @@ int muca_batch_submit(muca_batch* b, const uint32_t* mode, const uint32_t* therm
         return poison_round(b, b->err);
     };
     hipError_t e;
+    b->host_in_graph = (b->flags & MUCA_BATCH_GRAPH) && chunk >= longest;
+    if (b->host_in_graph) {
+        // one captured graph per round shape: clear, upload, sweeps, download,
+        // then the host half of the round (merge check, Eq. 4) as a host node
+        auto* fargs = reinterpret_cast<muca::FastSweepArgs*>(hs + b->off_fargs);
+        auto* gargs = reinterpret_cast<muca::SweepArgs*>(hs + b->off_gargs);
+        for (uint32_t i = 0; i < count; ++i) {
+            if (mode[i] == MUCA_BATCH_SKIP)
+                continue;
+            muca_instance* h = b->m[i];
+            const uint32_t n = (uint32_t)total[i];
+            const char* dtab = static_cast<char*>(b->d_stage) + b->off_tables + b->table_off[i];
+            fargs[i] = muca::FastSweepArgs{h->d_spins, h->d_energy, reinterpret_cast<const uint32_t*>(dtab),
+                                           b->d_hist + b->hist_off[i], h->position / h->N, h->wpad,
+                                           h->p.walkers, h->p.seed, n, therm[i], 0u};
+            gargs[i] = muca::SweepArgs{h->d_spins, h->d_energy, reinterpret_cast<const uint64_t*>(dtab),
+                                       b->d_hist + b->hist_off[i], h->position / h->N, h->wpad,
+                                       h->p.walkers, h->p.seed, n, therm[i], 0u};
+        }
+        if (b->graph_key != key || !b->exec) {
+            drop_graph(b);
+            if ((e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+                return dev_fail("hipStreamBeginCapture", e);
+            int rc = MUCA_OK;
+            e = muca::launch_fill_u64(b->d_hist, b->hist_words, b->stream);
+            if (e == hipSuccess)
+                rc = enqueue_round(b, stage_used, groups);
+            if (e == hipSuccess && rc == MUCA_OK)
+                e = hipMemcpyAsync(b->h_hist, b->d_hist, b->hist_words * sizeof(uint64_t), hipMemcpyDeviceToHost,
+                                   b->stream);
+            if (e == hipSuccess && rc == MUCA_OK)
+                e = hipLaunchHostFunc(b->stream, host_finish_node, b);
+            hipGraph_t g = nullptr;
+            const hipError_t e2 = hipStreamEndCapture(b->stream, &g);
+            if (rc != MUCA_OK || e != hipSuccess || e2 != hipSuccess) {
+                if (g)
+                    (void)hipGraphDestroy(g);
+                if (rc != MUCA_OK)
+                    return poison_round(b, b->err);
+                return dev_fail("batch graph capture", e != hipSuccess ? e : e2);
+            }
+            b->graph = g;
+            if ((e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0)) != hipSuccess)
+                return dev_fail("hipGraphInstantiate", e);
+            b->graph_key = key;
+        }
+        b->launches = (uint32_t)groups.size();
+        if ((e = hipEventRecord(b->ev_start, b->stream)) != hipSuccess)
+            return dev_fail("hipEventRecord", e);
+        if ((e = hipGraphLaunch(b->exec, b->stream)) != hipSuccess)
+            return dev_fail("hipGraphLaunch", e);
+        if ((e = hipEventRecord(b->ev_stop, b->stream)) != hipSuccess)
+            return dev_fail("hipEventRecord", e);
+        if ((e = hipEventRecord(b->ev_done, b->stream)) != hipSuccess)
+            return dev_fail("hipEventRecord", e);
+        return MUCA_OK;
+    }
     if ((e = muca::launch_fill_u64(b->d_hist, b->hist_words, b->stream)) != hipSuccess)
         return dev_fail("histogram clear", e);
     if ((e = hipEventRecord(b->ev_start, b->stream)) != hipSuccess)
@@ -528,30 +621,8 @@ int muca_batch_submit(muca_batch* b, const uint32_t* mode, const uint32_t* therm
                                        b->d_hist + b->hist_off[i], h->position / h->N + s0, h->wpad,
                                        h->p.walkers, h->p.seed, n, th, 0u};
         }
-        const bool single = chunk >= longest;
-        if ((b->flags & MUCA_BATCH_GRAPH) && single) {
-            if (b->graph_key != key || !b->exec) {
-                drop_graph(b);
-                if ((e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
-                    return dev_fail("hipStreamBeginCapture", e);
-                const int rc = enqueue_round(b, stage_used, live);
-                hipGraph_t g = nullptr;
-                e = hipStreamEndCapture(b->stream, &g);
-                if (rc != MUCA_OK || e != hipSuccess) {
-                    if (g)
-                        (void)hipGraphDestroy(g);
-                    return rc != MUCA_OK ? poison_round(b, b->err) : dev_fail("hipStreamEndCapture", e);
-                }
-                b->graph = g;
-                if ((e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0)) != hipSuccess)
-                    return dev_fail("hipGraphInstantiate", e);
-                b->graph_key = key;
-            }
-            if ((e = hipGraphLaunch(b->exec, b->stream)) != hipSuccess)
-                return dev_fail("hipGraphLaunch", e);
-        } else if (enqueue_round(b, stage_used, live) != MUCA_OK) {
+        if (enqueue_round(b, stage_used, live) != MUCA_OK)
             return poison_round(b, b->err);
-        }
         b->launches += (uint32_t)live.size();
         // a further chunk rewrites the staged arguments once the upload is done
         if (s0 + chunk < longest && (e = hipStreamSynchronize(b->stream)) != hipSuccess)
@@ -602,23 +673,32 @@ int muca_batch_finish(muca_batch* b, muca_info* infos)
             return bfail(b, MUCA_ERR_DEVICE, std::string("hipEventElapsedTime: ") + hipGetErrorName(e));
     }
 
-    // -- host: per-member results
+    // -- host: per-member results (already applied by the graph's host node,
+    //    whose device time the round's kernel_ms then includes)
     int result = MUCA_OK;
+    if (b->host_in_graph) {
+        result = b->host_rc;
+        if (result != MUCA_OK)
+            b->err = b->host_err;
+        for (uint32_t i = 0; i < count; ++i)
+            if (b->mode[i] != MUCA_BATCH_SKIP) {
+                b->round_infos[i].kernel_ms = ms;
+                b->m[i]->last.kernel_ms = ms;
+            }
+    } else {
+        std::string why;
+        result = finish_members(b, ms, b->round_infos, &why);
+        if (result != MUCA_OK)
+            b->err = why;
+    }
     uint64_t attempts = 0;
     bool two_wave_ran = false;
     for (uint32_t i = 0; i < count; ++i) {
         if (b->mode[i] == MUCA_BATCH_SKIP)
             continue;
-        muca_instance* h = b->m[i];
-        std::memcpy(h->hist.data(), b->h_hist + b->hist_off[i], ((size_t)h->N + 1) * sizeof(uint64_t));
-        const int rc = finish_call(h, (uint64_t)b->therm[i] * h->N, (uint64_t)b->sweeps[i] * h->N,
-                                   b->mode[i] == MUCA_BATCH_ITERATE, ms,
-                                   b->launches, b->form[i], infos ? &infos[i] : nullptr);
-        if (rc != MUCA_OK && result == MUCA_OK) {
-            result = rc;
-            b->err = "member " + std::to_string(i) + ": " + h->err;
-        }
-        attempts += (uint64_t)h->p.walkers * h->N * b->total[i];
+        if (infos)
+            infos[i] = b->round_infos[i];
+        attempts += (uint64_t)b->m[i]->p.walkers * b->m[i]->N * b->total[i];
         two_wave_ran |= b->form[i] == kSplit;
     }
     if (b->launches && (b->flags & MUCA_BATCH_AUTOTUNE) && b->tuned_form < 0 && ms > 0.0f) {
