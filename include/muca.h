@@ -271,10 +271,15 @@ typedef struct muca_batch muca_batch;
 #define MUCA_BATCH_PRODUCTION 2u
 
 /* batch flags */
-#define MUCA_BATCH_GRAPH 0x1u     /* capture a round's device work in a HIP graph
-                                     and replay it while the round's shape (which
-                                     members run, their sweep counts and kernel
-                                     forms) is unchanged                        */
+#define MUCA_BATCH_GRAPH 0x1u     /* capture a whole round in a HIP graph --
+                                     histogram clear, staging upload, sweeps,
+                                     histogram download, and the host half of
+                                     every member's call (sum check, statistics,
+                                     Eq. 4) as a host node -- and replay it while
+                                     the round's shape (which members run, their
+                                     sweep counts and kernel forms) is unchanged;
+                                     rounds that need several launches per member
+                                     run without the graph                     */
 #define MUCA_BATCH_AUTOTUNE 0x2u  /* time the two-wave and one-wave kernel forms
                                      on the first two rounds and keep the faster
                                      (results do not depend on the choice)      */
