@@ -49,6 +49,12 @@ VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
 # neighbour reads, 3 adds, the energy change, the table index, the compare,
 # the conditional flip, the energy update, the histogram increment: 13).
 ALU_OPS_PER_ATTEMPT = 5 + 10 + 13
+# The second roof: LDS bytes per attempt the chain needs -- the threshold
+# gather (4 B) and the histogram counter's read-modify-write (4 + 4 B) -- plus
+# the random words handed over through LDS in the two-wave form (4 B written,
+# 4 B read).  Peak: 128 B per clock per CU.
+LDS_BYTES_PER_ATTEMPT = {2: 4 + 8 + 8, 1: 4 + 8, 0: 8 + 8}
+LDS_PEAK_BYTES = 256 * 128 * 2.4e9
 
 
 def nearest_rank(values, q):
@@ -173,23 +179,45 @@ def profile_pass(Solver, wl, ln_g, sweeps=50):
                       "kernel_source_sha256_16": kernel_source_hash()}), flush=True)
 
 
-def cpu_baseline(wl, ln_g, sweeps, warm):
+def cpu_full_solve(wl, iter_cap, seed=1):
+    """The weight iteration of one solve of the workload on the CPU oracle (all
+    host threads), to the first flat iteration: its wall time (the oracle's
+    time to converged weights).  The production run is left out: at 10^4 +
+    10^4 sweeps it would take the oracle about ten more minutes."""
     import oracle
     L, W = wl["L"], wl["walkers"]
-    o = oracle.OracleMuca(L, W, 12345)
+    t0 = time.perf_counter()
+    o = oracle.OracleMuca(L, W, seed)
+    it = 0
+    while it < iter_cap:
+        info = o.iterate(wl["therm_sweeps"], wl["iter_sweeps"])
+        it += 1
+        print("oracle iteration %d: flatness %.3f, %.0f s" % (it, info["flatness"],
+              time.perf_counter() - t0), file=sys.stderr, flush=True)
+        if info["flatness"] >= wl["min_flat"]:
+            break
+    t_w = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
+    return {"seed": seed, "iterations": it, "ttcw_s": t_w, "cores": threads, "kind": "oracle"}
+
+
+def cpu_baseline(wl, ln_g, sweeps, warm, nthreads=0):
+    import oracle
+    L, W = wl["L"], wl["walkers"]
+    o = oracle.OracleMuca(L, W, 12345, nthreads=nthreads)
     o.set_log_weights(np.where(np.isfinite(ln_g), -ln_g, 0.0))
     o.production(0, warm)
     t = time.perf_counter()
     info = o.production(0, sweeps)
     dt = time.perf_counter() - t
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
+    threads = nthreads or int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
     return {
         "value": info["attempts"] / dt,
         "unit": "attempts/s",
         "cores": threads,
         "kind": "oracle",
-        "sample": "L=32, %d walkers, %d sweeps after %d warm-up sweeps at exact weights "
-                  "omega = -ln g (%.2e attempts, %.1f s)" % (W, sweeps, warm, info["attempts"], dt),
+        "sample": "L=%d, %d walkers, %d sweeps after %d warm-up sweeps at exact weights "
+                  "omega = -ln g (%.2e attempts, %.1f s)" % (L, W, sweeps, warm, info["attempts"], dt),
     }
 
 
@@ -501,6 +529,8 @@ def main():
     ap.add_argument("--cpu-sweeps", type=int, default=400)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-hardware-rate", action="store_true")
+    ap.add_argument("--cpu-full-solve", action="store_true",
+                    help="also time one whole solve of the workload on the CPU oracle (minutes)")
     ap.add_argument("--workload", default=WORKLOAD,
                     choices=[WORKLOAD, "batched48", "served_poisson20", "paper_schedule_L32",
                              "production_L32"],
@@ -617,11 +647,20 @@ def main():
             "ops_per_attempt": ALU_OPS_PER_ATTEMPT,
         },
     }
+    lds_rate = LDS_BYTES_PER_ATTEMPT[main_variant] * attempts_per_launch / avg_launch_s
+    out["roofline_lds"] = {"achieved": lds_rate / 1e12, "peak": LDS_PEAK_BYTES / 1e12, "unit": "TB/s",
+                           "frac": lds_rate / LDS_PEAK_BYTES,
+                           "bytes_per_attempt": LDS_BYTES_PER_ATTEMPT[main_variant]}
     if not args.no_hardware_rate and ln_g is not None:
         rate, ms = hardware_rate(Solver, wl, ln_g)
         out["exact_weights_attempts_per_s"] = rate
     if not args.no_cpu_baseline and ln_g is not None:
         out["cpu_baseline"] = cpu_baseline(wl, ln_g, args.cpu_sweeps, 2)
+        one = cpu_baseline(wl, ln_g, max(1, args.cpu_sweeps // 16), 1, nthreads=1)
+        out["cpu_baseline_one_core"] = {"value": one["value"], "unit": one["unit"], "cores": 1,
+                                        "sample": one["sample"]}
+    if args.cpu_full_solve:
+        out["cpu_full_solve"] = cpu_full_solve(wl, args.iter_cap)
     print(json.dumps(out), flush=True)
 
 
