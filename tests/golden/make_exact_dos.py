@@ -7,8 +7,15 @@ Sec. 3.3).  Values come only from ``oracle.exact_dos`` (Kaufman's closed
 form); for L <= 8 the transfer-matrix count and for L = 4 brute-force
 enumeration must agree with it before a file is written.
 
-Run from the repository root:  python tests/golden/make_exact_dos.py [L ...]
+For large L (--log) the table holds ln g(E) as IEEE doubles (17 significant
+digits; "-inf" where g = 0) instead of the exact integers, which run to
+thousands of digits; the integers are still checked (sum 2^N, E <-> -E
+symmetry) before the logarithms are written.
+
+Run from the repository root:  python tests/golden/make_exact_dos.py [--log] [L ...]
+(L = 64 takes about 40 minutes.)
 """
+import math
 import os
 import sys
 import time
@@ -46,7 +53,28 @@ def write(L):
     print("L=%d written in %.1fs" % (L, time.time() - t0), flush=True)
 
 
+def write_log(L, g=None):
+    t0 = time.time()
+    if g is None:
+        g = exact_dos.kaufman_dos(L)
+    N = L * L
+    assert sum(g) == 2 ** N
+    assert all(g[k] == g[N - k] for k in range(N + 1))
+    path = os.path.join(HERE, "ising_lndos_L%d.txt" % L)
+    with open(path, "w") as f:
+        f.write("# ln of the exact density of states g(E), periodic %dx%d Ising model, J=1\n" % (L, L))
+        f.write("# line k (after the header) = ln g(E) for E = -%d + 4k, k = 0..%d\n" % (2 * N, N))
+        f.write("# source: oracle.exact_dos (Kaufman closed form, inverse DFT); exact integers\n")
+        f.write("# checked (sum = 2^%d, E <-> -E symmetry), then ln taken in double precision\n" % N)
+        f.write("# written by tests/golden/make_exact_dos.py --log\n")
+        for v in g:
+            f.write(("%.17g\n" % math.log(v)) if v > 0 else "-inf\n")
+    print("ln g for L=%d written in %.1fs" % (L, time.time() - t0), flush=True)
+
+
 if __name__ == "__main__":
-    sizes = [int(a) for a in sys.argv[1:]] or DEFAULT_SIZES
+    args = sys.argv[1:]
+    as_log = "--log" in args
+    sizes = [int(a) for a in args if a != "--log"] or DEFAULT_SIZES
     for L in sizes:
-        write(L)
+        (write_log if as_log else write)(L)

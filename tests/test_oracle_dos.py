@@ -12,7 +12,10 @@ drawing the flipped clusters by hand:
   g(E_min + 16) = N(N-1) + 10N       two separated single flips, straight and
                                      bent trimers, 2x2 squares (L >= 6)
 """
+import math
 import os
+
+import numpy as np
 
 import pytest
 
@@ -67,3 +70,23 @@ def test_ln_dos_helper():
     ln = exact_dos.ln_dos(g)
     assert ln[1] == float("-inf")
     assert abs(ln[8] - 9.9293502) < 1e-6    # ln 20524
+
+
+def test_golden_log_table_L64(golden_dir):
+    # the L = 64 table holds ln g (the integers run to 1233 digits): the same
+    # hand-counted low-energy values, the E <-> -E symmetry and the total 2^N
+    path = os.path.join(golden_dir, "ising_lndos_L64.txt")
+    with open(path) as f:
+        lng = np.array([float(x) for x in f if not x.startswith("#")])
+    L, N = 64, 64 * 64
+    assert lng.size == N + 1
+    assert np.array_equal(lng, lng[::-1])
+    assert lng[0] == math.log(2) and lng[1] == -np.inf and lng[N - 1] == -np.inf
+    assert abs(lng[2] - math.log(2 * N)) < 1e-15 * math.log(2 * N)
+    assert abs(lng[3] - math.log(4 * N)) < 1e-15 * math.log(4 * N)
+    assert abs(lng[4] - math.log(N * (N - 1) + 10 * N)) < 1e-14
+    fin = np.isfinite(lng)
+    assert fin.sum() == N - 1
+    mx = lng[fin].max()
+    total = mx + math.log(np.exp(lng[fin] - mx).sum())
+    assert abs(total - N * math.log(2)) < 1e-9 * N
