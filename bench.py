@@ -102,6 +102,7 @@ def solve(Solver, wl, seed, iter_cap):
         v = info["kernel_variant"]
         variant_ms[v] = variant_ms.get(v, 0.0) + info["kernel_ms"]
 
+    last_note = time.perf_counter()
     while it < iter_cap:
         info = s.iterate(wl["therm_sweeps"], wl["iter_sweeps"])
         it += 1
@@ -109,6 +110,10 @@ def solve(Solver, wl, seed, iter_cap):
         if info["flatness"] >= wl["min_flat"]:
             converged = True
             break
+        if time.perf_counter() - last_note > 30.0:
+            print("  seed %d: iteration %d, visited %d bins, flatness %.3f" %
+                  (seed, it, info["visited_bins"], info["flatness"]), file=sys.stderr, flush=True)
+            last_note = time.perf_counter()
     t_conv = time.perf_counter()
     account(s.production(wl["prod_therm_sweeps"], wl["prod_sweeps"]))
     lng = s.log_dos(0) if converged else None
