@@ -112,7 +112,8 @@ typedef struct muca_info {
     double chebyshev;       /* Eq. A.1: max |H/m - 1|, m = sum H / (N-1)     */
     double kernel_ms;       /* device time of the sweep launches (HIP events) */
     uint32_t kernel_launches; /* sweep kernel launches of the call           */
-    uint32_t kernel_variant;  /* 0: generic, 1: fast, 2: split sweep kernel  */
+    uint32_t kernel_variant;  /* 0: generic, 1: fast, 2: split, 3: wide
+                                 sweep kernel (the last of the call)         */
     uint32_t width;           /* bins from the lowest to the highest visited
                                  bin of H, inclusive (full range: N + 1)     */
     uint32_t reserved;

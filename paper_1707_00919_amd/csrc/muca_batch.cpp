@@ -40,7 +40,7 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 thread_local std::string g_batch_error;
 
 // kernel forms, as in muca_info::kernel_variant
-constexpr uint32_t kGeneric = 0, kFast = 1, kSplit = 2;
+constexpr uint32_t kGeneric = 0, kFast = 1, kSplit = 2, kWide = 3;
 
 struct Group {
     uint32_t L = 0;
@@ -189,6 +189,8 @@ int enqueue_round(muca_batch* b, size_t stage_used, const std::vector<Group>& gr
         hipError_t e;
         if (G.form == kSplit)
             e = muca::launch_split_batch(G.L, fargs, items + G.first_item, G.nitems, s);
+        else if (G.form == kWide)
+            e = muca::launch_wide_batch(G.L, fargs, items + G.first_item, G.nitems, s);
         else if (G.form == kFast)
             e = muca::launch_fast_batch(G.L, fargs, items + G.first_item, G.nitems, s);
         else
@@ -448,10 +450,14 @@ int muca_batch_submit(muca_batch* b, const uint32_t* mode, const uint32_t* therm
             chunk = std::min(chunk, cap);
         compute_thresholds(h->N, h->omega.data(), h->table5.data());
         void* tab = hs + b->off_tables + b->table_off[i];
-        const bool fast_ok = !(h->p.flags & MUCA_FLAG_GENERIC_KERNEL) &&
+        const bool wide_ok = !(h->p.flags & MUCA_FLAG_GENERIC_KERNEL) && muca::wide_sweep_supported(h->L) &&
+                             fast_table(h->N, h->table5.data(), static_cast<uint32_t*>(tab), 8);
+        const bool fast_ok = !wide_ok && !(h->p.flags & MUCA_FLAG_GENERIC_KERNEL) &&
                              (muca::split_sweep_supported(h->L) || muca::fast_sweep_supported(h->L)) &&
-                             fast_table(h->N, h->table5.data(), static_cast<uint32_t*>(tab));
-        if (fast_ok) {
+                             fast_table(h->N, h->table5.data(), static_cast<uint32_t*>(tab), 5);
+        if (wide_ok) {
+            form[i] = kWide;
+        } else if (fast_ok) {
             form[i] = kFast;  // two-wave or one-wave decided below
         } else {
             device_table(h->N, h->table5.data(), static_cast<uint64_t*>(tab));

@@ -17,6 +17,11 @@
 // the walker in is counted one attempt later, after the next loads are
 // issued, since LDS answers a wave's requests in order.
 //
+// Where the records live is a Records policy: LdsRecords (28-byte records in
+// LDS, counter inside, L <= 64) or GlobalRecords (32-byte threshold records in
+// global memory, read through the caches, with the counters alone in LDS --
+// for L > 64, whose tables do not fit in LDS).
+//
 // The random words come from a Draws source: first() returns the four Philox
 // words of block 0 of the current loop step, and advance<B, PART>(rn), called
 // at the attempts with P & 3 = PART = 0..3 of the block before B, delivers
@@ -44,21 +49,80 @@ struct ChainShape {
     static constexpr int REC_BYTES = REC * (N + 1);
 };
 
+// 28-byte records in LDS: z = 28k + 8, threshold of m at z + 4(m - 2),
+// counter at z + 12.
+struct LdsRecords {
+    static constexpr uint32_t STRIDE = 28;
+    uint8_t* lds;
+    __device__ __forceinline__ static uint32_t z_of(int k) { return 28u * (uint32_t)k + 8u; }
+    __device__ __forceinline__ static int k_of(uint32_t z) { return (int)((z - 8u) / 28u); }
+    __device__ __forceinline__ uint32_t thr(uint32_t z, int ms) const
+    {
+        const uint32_t byte = z + (uint32_t)(ms * 4);  // in range: ms * 4 >= -8 and z >= 8
+        return *reinterpret_cast<const uint32_t*>(lds + byte);
+    }
+    __device__ __forceinline__ void count(uint32_t z, uint32_t inc) const
+    {
+        atomicAdd(reinterpret_cast<uint32_t*>(lds + z + 12), inc);
+    }
+};
+
+// 32-byte threshold records in global memory (S by m at bytes 4m of record
+// k): z = 32k, threshold of m at z + 8 + 4(m - 2); the counter of bin k is
+// word k of an LDS array, at byte z / 8.
+struct GlobalRecords {
+    static constexpr uint32_t STRIDE = 32;
+    const uint8_t* table;
+    uint8_t* counters;
+    __device__ __forceinline__ static uint32_t z_of(int k) { return 32u * (uint32_t)k; }
+    __device__ __forceinline__ static int k_of(uint32_t z) { return (int)(z >> 5); }
+    __device__ __forceinline__ uint32_t thr(uint32_t z, int ms) const
+    {
+        // the byte offset is formed in 32 bits first (8 + 4 ms >= 0), so that
+        // no wrapped negative term is ever added to the 64-bit pointer
+        const uint32_t byte = z + (uint32_t)(8 + ms * 4);
+        return *reinterpret_cast<const uint32_t*>(table + byte);
+    }
+    __device__ __forceinline__ void count(uint32_t z, uint32_t inc) const
+    {
+        atomicAdd(reinterpret_cast<uint32_t*>(counters + (z >> 3)), inc);
+    }
+};
+
+// The chain's random words computed in place: block B of the loop step that
+// starts at Philox block blk0, its ten rounds spread 3 + 3 + 2 + 2 over the
+// four attempts before it is needed.
+struct PhiloxDraws {
+    uint32_t blk0, c1, c2, seed, walker;
+    PhiloxState next;
+    __device__ __forceinline__ Words4 first() const { return philox10(blk0, c1, c2, 0u, seed, walker); }
+    template <int B, int PART>
+    __device__ __forceinline__ void advance(Words4& rn)
+    {
+        if constexpr (PART == 0) {
+            next = PhiloxState{blk0 + (uint32_t)B, c1, c2, 0u, seed, walker};
+            philox_rounds<0, 3>(next);
+        } else if constexpr (PART == 1) {
+            philox_rounds<3, 6>(next);
+        } else if constexpr (PART == 2) {
+            philox_rounds<6, 8>(next);
+        } else {
+            philox_rounds<8, 10>(next);
+            rn = Words4{{next.c0, next.c1, next.c2, next.c3}};
+        }
+    }
+};
+
 template <int L>
 struct ChainState {
     RowBits<L> rb;
-    uint32_t z;          // byte address of the record of the current bin + 8
+    uint32_t z;          // the current bin's record address (Records::z_of)
     int ms;              // (anti-aligned neighbours of the next site) - 2
     uint32_t thr_keep;   // threshold S of the next site if the previous site
     uint32_t thr_flip;   // was kept / flipped (loads may still be in flight)
     bool prev_flip;      // the previous site flipped
     uint32_t inc_last;   // record flag of the attempt that left the walker in z
 };
-
-__device__ __forceinline__ uint32_t lds_u32(const uint8_t* lds, uint32_t byte)
-{
-    return *reinterpret_cast<const uint32_t*>(lds + byte);
-}
 
 // Fills the records: five thresholds S = T - 1 (by m) from table[k*5 + m], a
 // zeroed counter, a pad word.  All threads of the workgroup take part.
@@ -88,7 +152,7 @@ __device__ __forceinline__ void chain_records_flush(const uint8_t* lds, unsigned
 }
 
 // Walker state from its lattice and energy; no attempt counted yet.
-template <int L>
+template <int L, class R>
 __device__ __forceinline__ void chain_load(ChainState<L>& st, const uint32_t* mine, size_t stride, int32_t energy)
 {
     constexpr int WPR = ChainShape<L>::WPR;
@@ -99,24 +163,24 @@ __device__ __forceinline__ void chain_load(ChainState<L>& st, const uint32_t* mi
         st.rb.dn[j] = mine[(size_t)(WPR + j) * stride];
     }
     st.rb.f0 = 0u;
-    st.z = 28u * (uint32_t)((energy + 2 * L * L) >> 2) + 8u;
+    st.z = R::z_of((energy + 2 * L * L) >> 2);
     st.inc_last = 0u;
 }
 
 // Counts the bin of the launch's last attempt; returns the walker's energy.
-template <int L>
-__device__ __forceinline__ int32_t chain_finish(ChainState<L>& st, uint8_t* lds)
+template <int L, class R>
+__device__ __forceinline__ int32_t chain_finish(ChainState<L>& st, const R& recs)
 {
-    atomicAdd(reinterpret_cast<uint32_t*>(lds + st.z + 12), st.inc_last);
-    return 4 * (int32_t)((st.z - 8u) / 28u) - 2 * L * L;
+    recs.count(st.z, st.inc_last);
+    return 4 * (int32_t)R::k_of(st.z) - 2 * L * L;
 }
 
-template <int L>
-__device__ __forceinline__ void chain_row_begin(ChainState<L>& st, const uint8_t* lds)
+template <int L, class R>
+__device__ __forceinline__ void chain_row_begin(ChainState<L>& st, const R& recs)
 {
     rowbits_begin<L>(st.rb);
     st.ms = bond_count<L, 0>(st.rb.nb, vert_minus_two<L, 0>(st.rb));
-    st.thr_keep = lds_u32(lds, st.z + (uint32_t)(st.ms * 4));
+    st.thr_keep = recs.thr(st.z, st.ms);
     st.thr_flip = st.thr_keep;
     st.prev_flip = false;
 }
@@ -130,9 +194,9 @@ __device__ __forceinline__ void chain_row_begin(ChainState<L>& st, const uint8_t
 // barrier keeps the compiler from moving that pick, and the wait on LDS it
 // implies, above the new loads: each load then has a whole attempt of
 // independent work to hide behind.
-template <int L, int P, class Draws>
+template <int L, int P, class R, class Draws>
 __device__ __forceinline__ void chain_attempt(ChainState<L>& st, Words4& rc, Words4& rn, Draws& draws,
-                                              uint8_t* lds, uint32_t inc)
+                                              const R& recs, uint32_t inc)
 {
     using S = ChainShape<L>;
     constexpr int X = P % L;
@@ -146,7 +210,7 @@ __device__ __forceinline__ void chain_attempt(ChainState<L>& st, Words4& rc, Wor
     for (int w = 0; w < S::WPR; ++w)
         nbf[w] = st.rb.nb[w];
     bond_flip<L, X>(nbf);
-    const uint32_t zf = st.z - (uint32_t)(st.ms * 28);
+    const uint32_t zf = st.z - (uint32_t)(st.ms * (int)R::STRIDE);
     int ms_keep = 0, ms_flip = 0;
     uint32_t next_keep = 0u, next_flip = 0u;
     if constexpr (X + 1 < L) {
@@ -169,10 +233,10 @@ __device__ __forceinline__ void chain_attempt(ChainState<L>& st, Words4& rc, Wor
         const int v1 = vert_minus_two<L, X + 1>(st.rb);
         ms_keep = bond_count<L, X + 1>(nbk, v1);
         ms_flip = bond_count<L, X + 1>(nbkf, v1);
-        next_keep = lds_u32(lds, st.z + (uint32_t)(ms_keep * 4));
-        next_flip = lds_u32(lds, zf + (uint32_t)(ms_flip * 4));
+        next_keep = recs.thr(st.z, ms_keep);
+        next_flip = recs.thr(zf, ms_flip);
     }
-    atomicAdd(reinterpret_cast<uint32_t*>(lds + st.z + 12), X == 0 ? st.inc_last : inc);
+    recs.count(st.z, X == 0 ? st.inc_last : inc);
     __builtin_amdgcn_sched_barrier(0);
     const uint32_t thr = st.prev_flip ? st.thr_flip : st.thr_keep;
     const bool accept = r <= thr;
@@ -192,18 +256,18 @@ __device__ __forceinline__ void chain_attempt(ChainState<L>& st, Words4& rc, Wor
     }
 }
 
-template <int L, int RR, class Draws, int... Xs>
+template <int L, int RR, class R, class Draws, int... Xs>
 __device__ __forceinline__ void chain_row_sites(ChainState<L>& st, Words4& rc, Words4& rn, Draws& draws,
-                                                uint8_t* lds, uint32_t inc, std::integer_sequence<int, Xs...>)
+                                                const R& recs, uint32_t inc, std::integer_sequence<int, Xs...>)
 {
-    (chain_attempt<L, RR * L + Xs>(st, rc, rn, draws, lds, inc), ...);
+    (chain_attempt<L, RR * L + Xs>(st, rc, rn, draws, recs, inc), ...);
 }
 
 // Row RR of a loop step that starts at row y: prefetch row y+RR+2, run the
 // row's L attempts, write the row back and slide the window down by one.
-template <int L, int RR, class Draws>
+template <int L, int RR, class R, class Draws>
 __device__ __forceinline__ void chain_row(ChainState<L>& st, Words4& rc, Words4& rn, Draws& draws,
-                                          uint8_t* lds, uint32_t inc, uint32_t* mine, size_t stride, int y)
+                                          const R& recs, uint32_t inc, uint32_t* mine, size_t stride, int y)
 {
     constexpr int WPR = ChainShape<L>::WPR;
     const int yy = y + RR;
@@ -212,8 +276,8 @@ __device__ __forceinline__ void chain_row(ChainState<L>& st, Words4& rc, Words4&
 #pragma unroll
     for (int j = 0; j < WPR; ++j)
         nx[j] = mine[(size_t)(ynext * WPR + j) * stride];
-    chain_row_begin<L>(st, lds);
-    chain_row_sites<L, RR>(st, rc, rn, draws, lds, inc, std::make_integer_sequence<int, L>{});
+    chain_row_begin<L>(st, recs);
+    chain_row_sites<L, RR>(st, rc, rn, draws, recs, inc, std::make_integer_sequence<int, L>{});
     rowbits_end<L>(st.rb);
 #pragma unroll
     for (int j = 0; j < WPR; ++j) {

@@ -119,13 +119,18 @@ hipError_t launch_fast_sweep(uint32_t L, const FastSweepArgs& a, hipStream_t s);
 bool split_sweep_supported(uint32_t L);
 hipError_t launch_split_sweep(uint32_t L, const FastSweepArgs& a, hipStream_t s);
 hipError_t launch_init(const InitArgs& a, hipStream_t s);
+// L > 64 with the thresholds in global memory: table holds, per bin k, S =
+// T - 1 of the move with m anti-aligned neighbours at table[k*8 + m]
+// (32-byte records; valid when no reachable T is 0).
+bool wide_sweep_supported(uint32_t L);
+hipError_t launch_wide_sweep(uint32_t L, const FastSweepArgs& a, hipStream_t s);
 hipError_t launch_sweep(uint32_t L, const SweepArgs& a, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* p, size_t n, hipStream_t s);
 
 // Arguments of a partial sweep: sites [site_begin, site_end) of one sweep, in
 // typewriter order, the sites from rec_begin on counted in the histogram.
-// table is in the generic layout (uint64, 4 per bin) or, with fast_table set,
-// in the fast layout (uint32 S = T - 1, 5 per bin).
+// table is in the generic layout (uint64, 4 per bin; table_stride 0) or holds
+// uint32 S = T - 1 by m, table_stride words per bin (5, or 8 for L > 64).
 struct RangeArgs {
     uint32_t* spins;
     int32_t* energy;
@@ -134,7 +139,7 @@ struct RangeArgs {
     uint64_t sweep;
     uint32_t L, wpad, walkers, seed;
     uint32_t site_begin, site_end, rec_begin;
-    uint32_t fast_table;
+    uint32_t table_stride;
 };
 hipError_t launch_sweep_range(const RangeArgs& a, hipStream_t s);
 
@@ -144,6 +149,8 @@ hipError_t launch_sweep_batch(uint32_t L, const SweepArgs* args, const BatchItem
                               uint32_t nitems, hipStream_t s);
 hipError_t launch_fast_batch(uint32_t L, const FastSweepArgs* args, const BatchItem* items,
                              uint32_t nitems, hipStream_t s);
+hipError_t launch_wide_batch(uint32_t L, const FastSweepArgs* args, const BatchItem* items, uint32_t nitems,
+                             hipStream_t s);
 hipError_t launch_split_batch(uint32_t L, const FastSweepArgs* args, const BatchItem* items,
                               uint32_t nitems, hipStream_t s);
 

@@ -247,7 +247,7 @@ __global__ __launch_bounds__(64) void sweep_range_kernel(RangeArgs a)
         const uint32_t r = philox10(i >> 2, c1, c2, 0u, a.seed, w).w[i & 3u];
         bool accept;
         if constexpr (kFast) {
-            accept = r <= static_cast<const uint32_t*>(a.table)[k * 5 + (int)m];
+            accept = r <= static_cast<const uint32_t*>(a.table)[k * (int)a.table_stride + (int)m];
         } else {
             const uint32_t slot = m - (m > 2u ? 1u : 0u);
             accept = (m == 2u) || ((uint64_t)r < static_cast<const uint64_t*>(a.table)[k * 4 + (int)slot]);
@@ -353,7 +353,7 @@ hipError_t launch_sweep_range(const RangeArgs& a, hipStream_t s)
     // one 32-bit counter per bin: up to 64 KiB + 4 B at L = 128
     const size_t lds = ((size_t)a.L * a.L + 1) * sizeof(uint32_t);
     constexpr int kMaxLds = 128 * 128 * 4 + 4;
-    if (a.fast_table) {
+    if (a.table_stride) {
         static const hipError_t attr = hipFuncSetAttribute(
             reinterpret_cast<const void*>(&sweep_range_kernel<true>), hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
         if (attr != hipSuccess)

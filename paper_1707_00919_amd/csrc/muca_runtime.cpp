@@ -146,19 +146,21 @@ void device_table(uint32_t N, const uint64_t* t5, uint64_t* t4)
 // configuration has E = -(2N-4) or 2N-4, Sec. 3).  Those entries are never
 // read and get 0.  Returns false when a move that can be proposed has T = 0:
 // r <= T - 1 cannot express "never", so the generic kernel must run.
-bool fast_table(uint32_t N, const uint64_t* t5, uint32_t* f)
+bool fast_table(uint32_t N, const uint64_t* t5, uint32_t* f, uint32_t stride)
 {
     for (uint32_t k = 0; k <= N; ++k) {
+        for (uint32_t m = 5; m < stride; ++m)
+            f[(size_t)k * stride + m] = 0u;
         for (int m = 0; m < 5; ++m) {
             const long kp = (long)k + 2 - m;
             const uint64_t t = t5[(size_t)k * 5 + (4 - m)];
             if (kp < 0 || kp > (long)N || k == 1 || k == N - 1 || kp == 1 || kp == (long)N - 1) {
-                f[(size_t)k * 5 + m] = 0u;
+                f[(size_t)k * stride + m] = 0u;
                 continue;
             }
             if (t == 0)
                 return false;
-            f[(size_t)k * 5 + m] = (uint32_t)(t - 1);
+            f[(size_t)k * stride + m] = (uint32_t)(t - 1);
         }
     }
     return true;
@@ -428,11 +430,14 @@ int run_attempts(muca_instance* h, uint64_t therm, uint64_t recorded, bool updat
         return fail(h, MUCA_ERR_OVERFLOW, "attempt position would wrap");
 
     compute_thresholds(N, h->omega.data(), h->table5.data());
-    // kernel choice: 2 split, 1 fast, 0 generic (all give the same bits)
+    // kernel choice: 3 wide, 2 split, 1 fast, 0 generic (all give the same bits)
     uint32_t variant = 0;
-    if (!(h->p.flags & MUCA_FLAG_GENERIC_KERNEL) &&
+    if (!(h->p.flags & MUCA_FLAG_GENERIC_KERNEL) && muca::wide_sweep_supported(h->L) &&
+        fast_table(N, h->table5.data(), reinterpret_cast<uint32_t*>(h->h_table4), 8)) {
+        variant = 3;
+    } else if (!(h->p.flags & MUCA_FLAG_GENERIC_KERNEL) &&
         (muca::split_sweep_supported(h->L) || muca::fast_sweep_supported(h->L)) &&
-        fast_table(N, h->table5.data(), reinterpret_cast<uint32_t*>(h->h_table4))) {
+        fast_table(N, h->table5.data(), reinterpret_cast<uint32_t*>(h->h_table4), 5)) {
         // The split kernel gives each 64 walkers a second wave for the random
         // numbers; once its workgroups no longer all fit at once, or more than
         // two share a CU, the one-wave form wins.
@@ -474,7 +479,7 @@ int run_attempts(muca_instance* h, uint64_t therm, uint64_t recorded, bool updat
             a.site_begin = g.site_begin;
             a.site_end = g.site_end;
             a.rec_begin = g.rec_begin;
-            a.fast_table = fast ? 1u : 0u;
+            a.table_stride = variant == 3 ? 8u : (fast ? 5u : 0u);
             MUCA_HIP(h, muca::launch_sweep_range(a, h->stream), "partial sweep launch");
             ++launches;
             continue;
@@ -495,8 +500,9 @@ int run_attempts(muca_instance* h, uint64_t therm, uint64_t recorded, bool updat
                 a.nsweeps = n;
                 a.therm = th;
                 MUCA_HIP(h,
-                         variant == 2 ? muca::launch_split_sweep(h->L, a, h->stream)
-                                      : muca::launch_fast_sweep(h->L, a, h->stream),
+                         variant == 3   ? muca::launch_wide_sweep(h->L, a, h->stream)
+                         : variant == 2 ? muca::launch_split_sweep(h->L, a, h->stream)
+                                        : muca::launch_fast_sweep(h->L, a, h->stream),
                          "sweep launch");
             } else {
                 muca::SweepArgs a{};

@@ -29,30 +29,6 @@
 namespace muca {
 namespace {
 
-// The chain's random words computed in place: block B of the loop step that
-// starts at Philox block blk0, its ten rounds spread 3 + 3 + 2 + 2 over the
-// four attempts before it is needed.
-struct PhiloxDraws {
-    uint32_t blk0, c1, c2, seed, walker;
-    PhiloxState next;
-    __device__ __forceinline__ Words4 first() const { return philox10(blk0, c1, c2, 0u, seed, walker); }
-    template <int B, int PART>
-    __device__ __forceinline__ void advance(Words4& rn)
-    {
-        if constexpr (PART == 0) {
-            next = PhiloxState{blk0 + (uint32_t)B, c1, c2, 0u, seed, walker};
-            philox_rounds<0, 3>(next);
-        } else if constexpr (PART == 1) {
-            philox_rounds<3, 6>(next);
-        } else if constexpr (PART == 2) {
-            philox_rounds<6, 8>(next);
-        } else {
-            philox_rounds<8, 10>(next);
-            rn = Words4{{next.c0, next.c1, next.c2, next.c3}};
-        }
-    }
-};
-
 // The chain of walker w (one lane) over all sweeps of the launch.
 template <int L>
 __device__ __forceinline__ void fast_chain(const FastSweepArgs& a, uint32_t w, uint8_t* lds)
@@ -61,7 +37,8 @@ __device__ __forceinline__ void fast_chain(const FastSweepArgs& a, uint32_t w, u
     uint32_t* const mine = a.spins + w;
     const size_t stride = a.wpad;
     ChainState<L> st;
-    chain_load<L>(st, mine, stride, a.energy[w]);
+    const LdsRecords recs{lds};
+    chain_load<L, LdsRecords>(st, mine, stride, a.energy[w]);
     const uint32_t live = w < a.walkers ? 1u : 0u;
     for (uint32_t t = 0; t < a.nsweeps; ++t) {
         const uint64_t sweep = a.sweep0 + t;
@@ -70,12 +47,12 @@ __device__ __forceinline__ void fast_chain(const FastSweepArgs& a, uint32_t w, u
             PhiloxDraws draws{(uint32_t)(y * L) >> 2, (uint32_t)sweep, (uint32_t)(sweep >> 32), a.seed, w, {}};
             Words4 rn = draws.first();
             Words4 rc;
-            chain_row<L, 0>(st, rc, rn, draws, lds, inc, mine, stride, y);
+            chain_row<L, 0>(st, rc, rn, draws, recs, inc, mine, stride, y);
             if constexpr (S::RPS == 2)
-                chain_row<L, 1>(st, rc, rn, draws, lds, inc, mine, stride, y);
+                chain_row<L, 1>(st, rc, rn, draws, recs, inc, mine, stride, y);
         }
     }
-    a.energy[w] = chain_finish<L>(st, lds);
+    a.energy[w] = chain_finish<L>(st, recs);
 }
 
 // One workgroup: `group` covers the 64-walker blocks group * G .. group * G +

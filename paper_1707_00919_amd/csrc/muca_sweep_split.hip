@@ -96,8 +96,9 @@ __device__ __forceinline__ void sweep_split_kernel_body(const FastSweepArgs& a, 
     const size_t stride = a.wpad;
     ChainState<L> st;
     const uint32_t live = w < a.walkers ? 1u : 0u;
+    const LdsRecords recs{lds};
     if (consumer)
-        chain_load<L>(st, mine, stride, a.energy[w]);
+        chain_load<L, LdsRecords>(st, mine, stride, a.energy[w]);
 
     for (uint32_t s = 0; s < steps; ++s) {
         if (consumer) {
@@ -107,16 +108,16 @@ __device__ __forceinline__ void sweep_split_kernel_body(const FastSweepArgs& a, 
             RingDraws draws{lds, S::REC_BYTES + (s & 1u) * S::SLOT_BYTES, lane};
             Words4 rn = draws.first();
             Words4 rc;
-            chain_row<L, 0>(st, rc, rn, draws, lds, inc, mine, stride, y);
+            chain_row<L, 0>(st, rc, rn, draws, recs, inc, mine, stride, y);
             if constexpr (S::RPS == 2)
-                chain_row<L, 1>(st, rc, rn, draws, lds, inc, mine, stride, y);
+                chain_row<L, 1>(st, rc, rn, draws, recs, inc, mine, stride, y);
         } else if (s + 1 < steps) {
             produce_step<L>(lds, s + 1, a, w, lane);
         }
         __syncthreads();
     }
     if (consumer)
-        a.energy[w] = chain_finish<L>(st, lds);
+        a.energy[w] = chain_finish<L>(st, recs);
     __syncthreads();
     chain_records_flush<L>(lds, a.hist, threadIdx.x, 2 * kWave);
 }
