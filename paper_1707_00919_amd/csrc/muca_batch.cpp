@@ -45,9 +45,16 @@ constexpr uint32_t kGeneric = 0, kFast = 1, kSplit = 2, kWide = 3;
 struct Group {
     uint32_t L = 0;
     uint32_t form = kGeneric;
+    uint32_t waves = 1;       // waves of 64 walkers per workgroup (one-wave form)
     uint32_t first_item = 0;  // index into the items array
     uint32_t nitems = 0;
 };
+
+// The autotuner's choices for members that can run the LDS-record kernels:
+// the two-wave form, the one-wave form with its default wave groups, or the
+// one-wave form with four waves (256 walkers) sharing each table.
+constexpr int kChoices = 3;
+constexpr int kTwoWave = 0, kOneWaveDefault = 1, kOneWaveFour = 2;
 
 }  // namespace
 
@@ -88,8 +95,9 @@ struct muca_batch {
     std::string host_err;
     // autotuner: attempts/ms of the two-wave and one-wave forms
     uint32_t round = 0;
-    double tuned_rate[2] = {0.0, 0.0};
+    double tuned_rate[kChoices] = {0.0, 0.0, 0.0};
     int tuned_form = -1;
+    int choice = kTwoWave;  // of the submitted round
     std::string err;
 };
 
@@ -192,7 +200,7 @@ int enqueue_round(muca_batch* b, size_t stage_used, const std::vector<Group>& gr
         else if (G.form == kWide)
             e = muca::launch_wide_batch(G.L, fargs, items + G.first_item, G.nitems, s);
         else if (G.form == kFast)
-            e = muca::launch_fast_batch(G.L, fargs, items + G.first_item, G.nitems, s);
+            e = muca::launch_fast_batch(G.L, G.waves, fargs, items + G.first_item, G.nitems, s);
         else
             e = muca::launch_sweep_batch(G.L, gargs, items + G.first_item, G.nitems, s);
         BATCH_HIP(b, e, "batched sweep launch");
@@ -445,7 +453,6 @@ int muca_batch_submit(muca_batch* b, const uint32_t* mode, const uint32_t* therm
         total[i] = (uint64_t)therm[i] + sweeps[i];
         ++active;
         active_blocks += h->wpad / muca::kWave;
-        chunk = std::min(chunk, muca::max_sweeps_per_launch(h->L));
         if (const uint32_t cap = h->p.flags & MUCA_FLAG_SWEEPS_PER_LAUNCH_MASK)
             chunk = std::min(chunk, cap);
         compute_thresholds(h->N, h->omega.data(), h->table5.data());
@@ -477,27 +484,31 @@ int muca_batch_submit(muca_batch* b, const uint32_t* mode, const uint32_t* therm
         if (form[i] == kFast && muca::split_sweep_supported(b->m[i]->L))
             lds_share += (double)(b->m[i]->wpad / muca::kWave) *
                          std::max(0.5, 1.0 / (double)(muca::kLdsPerCu / muca::split_lds_bytes(b->m[i]->L)));
-    bool two_wave = active_blocks <= 2u * (uint32_t)b->cus && lds_share <= (double)b->cus;
-    if (b->flags & MUCA_BATCH_AUTOTUNE) {
-        if (b->tuned_form >= 0)
-            two_wave = b->tuned_form == 1;
-        else
-            two_wave = (b->round % 2) == 0;
-    }
+    const bool two_wave = active_blocks <= 2u * (uint32_t)b->cus && lds_share <= (double)b->cus;
+    b->choice = two_wave ? kTwoWave : kOneWaveDefault;
+    if (b->flags & MUCA_BATCH_AUTOTUNE)
+        b->choice = b->tuned_form >= 0 ? b->tuned_form : (int)(b->round % kChoices);
+    std::vector<uint32_t> waves(count, 1u);
     for (uint32_t i = 0; i < count; ++i) {
-        if (form[i] != kFast)
-            continue;
         const uint32_t L = b->m[i]->L;
-        const bool want_fast = (b->m[i]->p.flags & MUCA_FLAG_FAST_KERNEL) != 0 || !two_wave;
-        if (muca::split_sweep_supported(L) && !(want_fast && muca::fast_sweep_supported(L)))
-            form[i] = kSplit;
-        else
-            form[i] = kFast;
+        if (form[i] == kFast) {
+            const bool want_fast = (b->m[i]->p.flags & MUCA_FLAG_FAST_KERNEL) != 0 || b->choice != kTwoWave;
+            if (muca::split_sweep_supported(L) && !(want_fast && muca::fast_sweep_supported(L))) {
+                form[i] = kSplit;
+            } else {
+                form[i] = kFast;
+                waves[i] = b->choice == kOneWaveFour ? 4u : muca::fast_waves_per_group(L);
+            }
+        }
+        // a launch stays below 2^32 counts per LDS counter of a workgroup
+        if (mode[i] != MUCA_BATCH_SKIP)
+            chunk = std::min(chunk, muca::max_sweeps_per_launch(L, waves[i]));
     }
 
     // -- groups and work items; within a group the members with the most
     //    sweeps come first so that their workgroups start first
     std::map<std::pair<uint32_t, uint32_t>, std::vector<uint32_t>> by_group;  // (L, form) -> members
+    // (within a round every member of one (L, form) has the same wave count)
     for (uint32_t i = 0; i < count; ++i)
         if (mode[i] != MUCA_BATCH_SKIP)
             by_group[{b->m[i]->L, form[i]}].push_back(i);
@@ -511,18 +522,19 @@ int muca_batch_submit(muca_batch* b, const uint32_t* mode, const uint32_t* therm
         Group G;
         G.L = it->first.first;
         G.form = it->first.second;
+        G.waves = waves[mem.front()];
         G.first_item = nitems;
         for (uint32_t i : mem) {
             // a work item is one workgroup: 64 walkers, or for the one-wave form
             // fast_waves_per_group(L) blocks of 64 that share one table
             const uint32_t blocks = b->m[i]->wpad / muca::kWave;
-            const uint32_t per = G.form == kFast ? muca::fast_waves_per_group(G.L) : 1u;
+            const uint32_t per = G.form == kFast ? G.waves : 1u;
             for (uint32_t blk = 0; blk < (blocks + per - 1) / per; ++blk)
                 items[nitems++] = muca::BatchItem{i, blk};
             key += std::to_string(i) + ":" + std::to_string(total[i]) + ",";
         }
         G.nitems = nitems - G.first_item;
-        key += "|" + std::to_string(G.L) + "/" + std::to_string(G.form) + ";";
+        key += "|" + std::to_string(G.L) + "/" + std::to_string(G.form) + "/" + std::to_string(G.waves) + ";";
         groups.push_back(G);
     }
     if (int rc = ensure_group_streams(b, groups.size()))
@@ -698,19 +710,22 @@ int muca_batch_finish(muca_batch* b, muca_info* infos)
             b->err = why;
     }
     uint64_t attempts = 0;
-    bool two_wave_ran = false;
     for (uint32_t i = 0; i < count; ++i) {
         if (b->mode[i] == MUCA_BATCH_SKIP)
             continue;
         if (infos)
             infos[i] = b->round_infos[i];
         attempts += (uint64_t)b->m[i]->p.walkers * b->m[i]->N * b->total[i];
-        two_wave_ran |= b->form[i] == kSplit;
     }
     if (b->launches && (b->flags & MUCA_BATCH_AUTOTUNE) && b->tuned_form < 0 && ms > 0.0f) {
-        b->tuned_rate[two_wave_ran ? 1 : 0] = (double)attempts / ms;
-        if (b->round >= 1)
-            b->tuned_form = b->tuned_rate[1] >= b->tuned_rate[0] ? 1 : 0;
+        b->tuned_rate[b->choice] = (double)attempts / ms;
+        if (b->round + 1 >= (uint32_t)kChoices) {
+            int best = 0;
+            for (int c = 1; c < kChoices; ++c)
+                if (b->tuned_rate[c] > b->tuned_rate[best])
+                    best = c;
+            b->tuned_form = best;
+        }
     }
     if (b->launches)
         ++b->round;

@@ -104,11 +104,13 @@ inline bool prefer_split(uint32_t L, uint64_t blocks, uint32_t cus)
 }
 
 // Largest number of recorded sweeps one launch may run without a 32-bit LDS
-// histogram counter overflowing: every walker of a workgroup (up to
-// 64 * fast_waves_per_group(L)) adds N counts per sweep to the same table.
-inline uint32_t max_sweeps_per_launch(uint32_t L)
+// histogram counter overflowing: every walker of a workgroup (64 per wave,
+// waves_per_group waves; by default fast_waves_per_group(L)) adds N counts
+// per sweep to the same table.
+inline uint32_t max_sweeps_per_launch(uint32_t L, uint32_t waves_per_group = 0)
 {
-    const uint64_t per_sweep = (uint64_t)kWave * fast_waves_per_group(L) * L * L;
+    const uint32_t G = waves_per_group ? waves_per_group : fast_waves_per_group(L);
+    const uint64_t per_sweep = (uint64_t)kWave * G * L * L;
     const uint64_t m = 0xffffffffull / per_sweep;
     return m > 0x7fffffffull ? 0x7fffffffu : (uint32_t)m;
 }
@@ -147,7 +149,8 @@ hipError_t launch_sweep_range(const RangeArgs& a, hipStream_t s);
 // items[i], all members of the batch having the same L.
 hipError_t launch_sweep_batch(uint32_t L, const SweepArgs* args, const BatchItem* items,
                               uint32_t nitems, hipStream_t s);
-hipError_t launch_fast_batch(uint32_t L, const FastSweepArgs* args, const BatchItem* items,
+// One-wave form with G (1, 2 or 4) waves of 64 walkers per workgroup.
+hipError_t launch_fast_batch(uint32_t L, uint32_t G, const FastSweepArgs* args, const BatchItem* items,
                              uint32_t nitems, hipStream_t s);
 hipError_t launch_wide_batch(uint32_t L, const FastSweepArgs* args, const BatchItem* items, uint32_t nitems,
                              hipStream_t s);

@@ -56,12 +56,13 @@ __device__ __forceinline__ void fast_chain(const FastSweepArgs& a, uint32_t w, u
 }
 
 // One workgroup: `group` covers the 64-walker blocks group * G .. group * G +
-// G - 1 (G = fast_waves_per_group(L)), one wave each, all sharing one record
-// table; waves past the instance's last block only help fill and drain it.
-template <int L>
+// G - 1, one wave each, all sharing one record table; waves past the
+// instance's last block only help fill and drain it.  G is
+// fast_waves_per_group(L) for single instances; batched rounds may run other
+// G (the batch autotuner's choice), with the same results.
+template <int L, int G>
 __device__ __forceinline__ void sweep_fast_kernel_body(const FastSweepArgs& a, uint32_t group)
 {
-    constexpr int G = (int)fast_waves_per_group(L);
     static_assert(ChainShape<L>::REC_BYTES == (int)fast_lds_bytes(L), "LDS size formula");
     __shared__ __attribute__((aligned(16))) uint8_t lds[ChainShape<L>::REC_BYTES];
 
@@ -80,22 +81,33 @@ __device__ __forceinline__ void sweep_fast_kernel_body(const FastSweepArgs& a, u
 template <int L>
 __global__ __launch_bounds__(64 * fast_waves_per_group(L)) void sweep_fast_kernel(FastSweepArgs a)
 {
-    sweep_fast_kernel_body<L>(a, blockIdx.x);
+    sweep_fast_kernel_body<L, (int)fast_waves_per_group(L)>(a, blockIdx.x);
 }
 
-template <int L>
-__global__ __launch_bounds__(64 * fast_waves_per_group(L)) void sweep_fast_kernel_batch(const FastSweepArgs* args,
-                                                                                       const BatchItem* items)
+template <int L, int G>
+__global__ __launch_bounds__(64 * G) void sweep_fast_kernel_batch(const FastSweepArgs* args, const BatchItem* items)
 {
     const BatchItem it = items[blockIdx.x];
-    sweep_fast_kernel_body<L>(args[it.member], it.block);
+    sweep_fast_kernel_body<L, G>(args[it.member], it.block);
 }
 
 template <int L>
-hipError_t launch_fast_L_batch_L(const FastSweepArgs* args, const BatchItem* items, uint32_t n, hipStream_t s)
+hipError_t launch_fast_L_batch_L(uint32_t G, const FastSweepArgs* args, const BatchItem* items, uint32_t n,
+                                 hipStream_t s)
 {
-    hipLaunchKernelGGL(sweep_fast_kernel_batch<L>, dim3(n), dim3(kWave * fast_waves_per_group(L)), 0, s, args,
-                       items);
+    switch (G) {
+    case 1:
+        hipLaunchKernelGGL((sweep_fast_kernel_batch<L, 1>), dim3(n), dim3(kWave), 0, s, args, items);
+        break;
+    case 2:
+        hipLaunchKernelGGL((sweep_fast_kernel_batch<L, 2>), dim3(n), dim3(2 * kWave), 0, s, args, items);
+        break;
+    case 4:
+        hipLaunchKernelGGL((sweep_fast_kernel_batch<L, 4>), dim3(n), dim3(4 * kWave), 0, s, args, items);
+        break;
+    default:
+        return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
@@ -139,15 +151,15 @@ hipError_t launch_fast_sweep(uint32_t L, const FastSweepArgs& a, hipStream_t s)
     }
 }
 
-hipError_t launch_fast_batch(uint32_t L, const FastSweepArgs* args, const BatchItem* items, uint32_t nitems,
-                             hipStream_t s)
+hipError_t launch_fast_batch(uint32_t L, uint32_t G, const FastSweepArgs* args, const BatchItem* items,
+                             uint32_t nitems, hipStream_t s)
 {
     if (nitems == 0)
         return hipSuccess;
     switch (L) {
 #define MUCA_CASE(LL) \
     case LL:          \
-        return launch_fast_L_batch_L<LL>(args, items, nitems, s);
+        return launch_fast_L_batch_L<LL>(G, args, items, nitems, s);
         MUCA_FAST_L(MUCA_CASE)
 #undef MUCA_CASE
     default:
