@@ -224,6 +224,18 @@ int muca_log_dos(const muca_instance* h, int normalization, double* out, size_t 
 /* Diagnostics of the most recent sweep call (zeros before the first).       */
 int muca_last_info(const muca_instance* h, muca_info* out);
 
+/* Checkpoint and resume.  The whole state of an instance -- lattices and
+ * energies of every walker, omega, the last histogram, the attempt position
+ * and the iteration statistics -- as one host byte array; with counter-based
+ * random numbers nothing else is needed, so an instance restored from it
+ * continues bit for bit as the original would.  muca_restore accepts only a
+ * checkpoint of an instance with the same L, walkers and seed (and rejects
+ * non-finite weights or impossible energies); n must equal
+ * muca_checkpoint_bytes(h).  Both calls block until the copies are done.   */
+size_t muca_checkpoint_bytes(const muca_instance* h);
+int muca_checkpoint(const muca_instance* h, void* out, size_t n);
+int muca_restore(muca_instance* h, const void* in, size_t n);
+
 /* Message for the last failure on h (NULL: the last failed muca_create of
  * this thread).  Valid until the next call on h.                            */
 const char* muca_last_error(const muca_instance* h);

@@ -118,6 +118,9 @@ PROTOTYPES = {
     "muca_log_dos": (_INT, [_P, _INT, _P, _SZ]),
     "muca_last_info": (_INT, [_P, ctypes.POINTER(MucaInfo)]),
     "muca_last_error": (ctypes.c_char_p, [_P]),
+    "muca_checkpoint_bytes": (_SZ, [_P]),
+    "muca_checkpoint": (_INT, [_P, _P, _SZ]),
+    "muca_restore": (_INT, [_P, _P, _SZ]),
     "muca_iterate_attempts": (_INT, [_P, ctypes.c_uint64, ctypes.c_uint64, ctypes.POINTER(MucaInfo)]),
     "muca_production_attempts": (_INT, [_P, ctypes.c_uint64, ctypes.c_uint64,
                                         ctypes.POINTER(MucaInfo)]),

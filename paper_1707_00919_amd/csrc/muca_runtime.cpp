@@ -828,6 +828,121 @@ int muca_spins(const muca_instance* h, int8_t* out, size_t n)
     return MUCA_OK;
 }
 
+namespace {
+
+// Checkpoint layout: a header, then omega[N+1] (double), hist[N+1] (uint64),
+// energies[wpad] (int32) and the lattice words[L * wpr * wpad] (uint32) in the
+// device layout (padding walkers included, so that a restored instance
+// continues bit for bit).
+struct CheckpointHeader {
+    uint32_t magic;    // 'MUCK'
+    uint32_t version;  // 1
+    uint32_t L, walkers, seed, wpad;
+    uint64_t position;
+    uint32_t iteration;
+    int32_t width_prev, reach_prev;
+    uint32_t reserved;
+};
+constexpr uint32_t kCheckpointMagic = 0x4b43554du;
+
+size_t checkpoint_bytes(const muca_instance* h)
+{
+    const size_t N1 = (size_t)h->N + 1;
+    return sizeof(CheckpointHeader) + N1 * sizeof(double) + N1 * sizeof(uint64_t) +
+           (size_t)h->wpad * sizeof(int32_t) + (size_t)h->L * h->wpr * h->wpad * sizeof(uint32_t);
+}
+
+}  // namespace
+
+size_t muca_checkpoint_bytes(const muca_instance* h)
+{
+    return h ? checkpoint_bytes(h) : 0;
+}
+
+int muca_checkpoint(const muca_instance* h, void* out, size_t n)
+{
+    int rc = check_live(h);
+    if (rc != MUCA_OK)
+        return rc;
+    muca_instance* m = const_cast<muca_instance*>(h);
+    if (!out || n != checkpoint_bytes(h))
+        return fail(m, MUCA_ERR_INVALID_ARG, "n must be muca_checkpoint_bytes(h)");
+    const size_t N1 = (size_t)h->N + 1;
+    char* p = static_cast<char*>(out);
+    CheckpointHeader hd{};
+    hd.magic = kCheckpointMagic;
+    hd.version = 1;
+    hd.L = h->L;
+    hd.walkers = h->p.walkers;
+    hd.seed = h->p.seed;
+    hd.wpad = h->wpad;
+    hd.position = h->position;
+    hd.iteration = h->iteration;
+    hd.width_prev = h->width_prev;
+    hd.reach_prev = h->reach_prev;
+    std::memcpy(p, &hd, sizeof hd);
+    p += sizeof hd;
+    std::memcpy(p, h->omega.data(), N1 * sizeof(double));
+    p += N1 * sizeof(double);
+    std::memcpy(p, h->hist.data(), N1 * sizeof(uint64_t));
+    p += N1 * sizeof(uint64_t);
+    MUCA_HIP(m, hipSetDevice(h->device), "hipSetDevice");
+    MUCA_HIP(m, hipMemcpyAsync(p, h->d_energy, (size_t)h->wpad * sizeof(int32_t), hipMemcpyDeviceToHost, h->stream),
+             "energy download");
+    p += (size_t)h->wpad * sizeof(int32_t);
+    MUCA_HIP(m, hipMemcpyAsync(p, h->d_spins, (size_t)h->L * h->wpr * h->wpad * sizeof(uint32_t),
+                               hipMemcpyDeviceToHost, h->stream),
+             "spin download");
+    MUCA_HIP(m, hipStreamSynchronize(h->stream), "checkpoint download");
+    return MUCA_OK;
+}
+
+int muca_restore(muca_instance* h, const void* in, size_t n)
+{
+    int rc = check_live(h);
+    if (rc != MUCA_OK)
+        return rc;
+    if (!in || n != checkpoint_bytes(h))
+        return fail(h, MUCA_ERR_INVALID_ARG, "n must be muca_checkpoint_bytes(h)");
+    const char* p = static_cast<const char*>(in);
+    CheckpointHeader hd;
+    std::memcpy(&hd, p, sizeof hd);
+    if (hd.magic != kCheckpointMagic || hd.version != 1)
+        return fail(h, MUCA_ERR_INVALID_ARG, "not a checkpoint of this library");
+    if (hd.L != h->L || hd.walkers != h->p.walkers || hd.seed != h->p.seed || hd.wpad != h->wpad)
+        return fail(h, MUCA_ERR_INVALID_ARG, "checkpoint of an instance with other L, walkers or seed");
+    const size_t N1 = (size_t)h->N + 1;
+    const double* om = reinterpret_cast<const double*>(p + sizeof hd);
+    for (size_t k = 0; k < N1; ++k) {
+        double v;
+        std::memcpy(&v, om + k, sizeof v);
+        if (!std::isfinite(v))
+            return fail(h, MUCA_ERR_INVALID_ARG, "checkpoint holds a non-finite log weight");
+    }
+    const char* pe = p + sizeof hd + N1 * (sizeof(double) + sizeof(uint64_t));
+    const int32_t lo = -2 * (int32_t)h->N, hi = 2 * (int32_t)h->N;
+    for (size_t w = 0; w < h->wpad; ++w) {
+        int32_t e;
+        std::memcpy(&e, pe + w * sizeof(int32_t), sizeof e);
+        if (e < lo || e > hi || (e - lo) % 4 != 0)
+            return fail(h, MUCA_ERR_INVALID_ARG, "checkpoint holds an impossible energy");
+    }
+    MUCA_HIP(h, hipSetDevice(h->device), "hipSetDevice");
+    MUCA_HIP(h, hipMemcpyAsync(h->d_energy, pe, (size_t)h->wpad * sizeof(int32_t), hipMemcpyHostToDevice, h->stream),
+             "energy upload");
+    MUCA_HIP(h, hipMemcpyAsync(h->d_spins, pe + (size_t)h->wpad * sizeof(int32_t),
+                               (size_t)h->L * h->wpr * h->wpad * sizeof(uint32_t), hipMemcpyHostToDevice, h->stream),
+             "spin upload");
+    MUCA_HIP(h, hipStreamSynchronize(h->stream), "checkpoint upload");
+    std::memcpy(h->omega.data(), p + sizeof hd, N1 * sizeof(double));
+    std::memcpy(h->hist.data(), p + sizeof hd + N1 * sizeof(double), N1 * sizeof(uint64_t));
+    h->position = hd.position;
+    h->iteration = hd.iteration;
+    h->width_prev = hd.width_prev;
+    h->reach_prev = hd.reach_prev;
+    return MUCA_OK;
+}
+
 int muca_log_dos(const muca_instance* h, int normalization, double* out, size_t n)
 {
     int rc = check_live(h);

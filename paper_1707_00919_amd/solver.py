@@ -159,6 +159,18 @@ class Solver:
         self._check(self._lib.muca_log_dos(self._h, normalization, _ptr(out), out.size))
         return out
 
+    def checkpoint(self):
+        """The instance's whole state as bytes (restore with ``restore``)."""
+        n = int(self._lib.muca_checkpoint_bytes(self._h))
+        buf = np.zeros(n, dtype=np.uint8)
+        self._check(self._lib.muca_checkpoint(self._h, _ptr(buf), n))
+        return buf.tobytes()
+
+    def restore(self, state):
+        """Continue from a checkpoint of an instance with the same L, walkers, seed."""
+        buf = np.frombuffer(state, dtype=np.uint8).copy()
+        self._check(self._lib.muca_restore(self._h, _ptr(buf), buf.size))
+
     def last_info(self):
         info = _abi.MucaInfo()
         self._check(self._lib.muca_last_info(self._h, ctypes.byref(info)))

@@ -299,3 +299,43 @@ def test_invalid_arguments_are_reported():
     with pytest.raises(MucaError) as e:
         s.log_dos(0)   # histogram of one sweep from omega = 0 misses the ground state
     assert e.value.code == _abi.MUCA_ERR_NOT_CONVERGED
+
+
+@pytest.mark.parametrize("L,W,seed", [(8, 100, 41), (32, 130, 42), (128, 64, 43)])
+def test_checkpoint_resume_continues_bit_exactly(L, W, seed):
+    # S1 + S2 attempts with a checkpoint/restore into a fresh instance between
+    # them equal the same run without one, and the oracle's run of S1 + S2
+    # (calls cut inside a sweep too)
+    note("checkpoint L=%d W=%d" % (L, W))
+    from paper_1707_00919_amd import MucaError, _abi
+    N = L * L
+    om = smooth_log_weights(L, seed)
+    a, c = Solver(L, W, seed), Solver(L, W, seed)
+    o = oracle.OracleMuca(L, W, seed)
+    for x in (a, c, o):
+        x.set_log_weights(om)
+    a.iterate(1, 2)
+    a.production_attempts(3, N + 7)
+    state = a.checkpoint()
+    b = Solver(L, W, seed)
+    b.restore(state)
+    a.iterate_attempts(0, 2 * N - 3)
+    b.iterate_attempts(0, 2 * N - 3)
+    c.iterate(1, 2)
+    c.production_attempts(3, N + 7)
+    c.iterate_attempts(0, 2 * N - 3)
+    o.iterate(1, 2)
+    o.production_attempts(3, N + 7)
+    o.iterate_attempts(0, 2 * N - 3)
+    for s in (a, b, c):
+        np.testing.assert_array_equal(s.histogram(), o.hist)
+        np.testing.assert_array_equal(bits(s.log_weights()), bits(o.omega))
+        np.testing.assert_array_equal(s.energies(), o.energies)
+        np.testing.assert_array_equal(s.spins(), o.spins)
+        assert s.last_info()["position"] == o.position
+    with pytest.raises(MucaError) as e:
+        Solver(L, W, seed + 1).restore(state)
+    assert e.value.code == _abi.MUCA_ERR_INVALID_ARG
+    with pytest.raises(MucaError) as e:
+        b.restore(state[:-4])
+    assert e.value.code == _abi.MUCA_ERR_INVALID_ARG
