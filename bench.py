@@ -550,7 +550,7 @@ def main():
     ap.add_argument("--serve-duration", type=float, default=60.0)
     ap.add_argument("--block-sweeps", type=int, default=1000)
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
-    ap.add_argument("--serve-max-walkers", type=int, default=1 << 17)
+    ap.add_argument("--serve-max-walkers", type=int, default=1 << 19)
     ap.add_argument("--serve-solo-sample", type=int, default=24,
                     help="solve this many of the first requests alone, one per launch, "
                          "for the comparison rate")
