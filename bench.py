@@ -137,8 +137,8 @@ def hardware_rate(Solver, wl, ln_g, warm_sweeps=20, timed_sweeps=200):
     return info["attempts"] / (info["kernel_ms"] * 1e-3), info["kernel_ms"] / info["kernel_launches"]
 
 
-KERNEL_SOURCES = ["muca_kernels.hip", "muca_sweep_fast.hip", "muca_sweep_split.hip",
-                  "muca_rowbits.h", "philox.h", "muca_device.h"]
+KERNEL_SOURCES = ["muca_kernels.hip", "muca_sweep_fast.hip", "muca_sweep_split.hip", "muca_sweep_wide.hip",
+                  "muca_chain.h", "muca_rowbits.h", "philox.h", "muca_device.h"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_sweep_L32_W16384.txt")
 COPY_BYTES = 256 << 20
 
