@@ -224,3 +224,27 @@ def test_batched_workload_full_size_sampled_walkers():
         o.production(1, 1)
         np.testing.assert_array_equal(m.energies()[ids], o.energies)
         np.testing.assert_array_equal(m.spins()[ids], o.spins)
+
+
+def test_batch_member_with_zero_threshold_runs_generic():
+    # a member whose table has a reachable T = 0 runs the generic kernel in
+    # its own group, next to members on the other forms; all match their
+    # solo runs
+    from paper_1707_00919_amd import Batch
+    note("batch with a zero-threshold member")
+    shapes = [(8, 64, 51), (16, 130, 52), (96, 64, 53)]
+    oms = [random_log_weights(L, s, scale=1.0) for L, _, s in shapes]
+    oms[0] = oms[0].copy()
+    oms[0][30:] -= 30.0
+    solo, grouped = make(shapes), make(shapes)
+    for a, b, om in zip(solo, grouped, oms):
+        a.set_log_weights(om)
+        b.set_log_weights(om)
+    batch = Batch(grouped)
+    infos = batch.run([2, 1, 1], [1, 0, 1], [2, 3, 2])
+    assert infos[0]["kernel_variant"] == 0 and infos[2]["kernel_variant"] == 3
+    solo[0].production(1, 2)
+    solo[1].iterate(0, 3)
+    solo[2].iterate(1, 2)
+    for a, b in zip(solo, grouped):
+        same(a, b)
