@@ -154,6 +154,23 @@ MUCA_BATCH_AUTOTUNE = 0x2
 _lib = None
 
 
+def _share_torch_runtime():
+    """Load torch (when installed) before libmuca.so.
+
+    torch ships its own HIP runtime, which its libraries find under the name
+    libamdhip64.so.  libmuca.so asks for libamdhip64.so.7, the soname torch's
+    copy also carries: loaded after torch, libmuca binds to torch's runtime;
+    loaded first, it would pull in the system runtime and torch would then
+    load its own beside it -- two HIP runtimes in one process, and the second
+    to open the device finds none.  Loading torch first keeps one runtime,
+    whose device memory and streams both sides then share.
+    """
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+
+
 def lib():
     """Load libmuca.so (raises if it has not been built)."""
     global _lib
@@ -161,6 +178,7 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise ImportError("libmuca.so not found at %s; build it with "
                               "`python -m paper_1707_00919_amd.build`" % LIB_PATH)
+        _share_torch_runtime()
         handle = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in PROTOTYPES.items():
             fn = getattr(handle, name)

@@ -92,3 +92,20 @@ def test_struct_layouts_match_header(tmp_path):
         for f, _ in py._fields_:
             want.append("%s %s %d" % (cname, f, getattr(py, f).offset))
     assert [g for g in got if g] == want
+
+
+def test_library_and_torch_share_one_hip_runtime():
+    """Loading the binding before torch must not leave two HIP runtimes in the
+    process (the second one to open the device would find none)."""
+    import subprocess
+    import sys
+    if not os.path.exists(_abi.LIB_PATH):
+        pytest.fail("libmuca.so is not built (run __graft_entry__.build())")
+    code = ("from paper_1707_00919_amd import _abi\n"
+            "_abi.lib()\n"
+            "import torch\n"
+            "maps = {l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l}\n"
+            "print(len(maps))\n")
+    out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip().splitlines()[-1] == "1"
