@@ -82,8 +82,12 @@ typedef enum muca_status {
  * thresholds and the histogram interleaved in LDS, random numbers from a
  * second wave, the next attempt's thresholds fetched ahead.  With more than
  * two of its workgroups (64 walkers each) per compute unit, or with FAST, the
- * one-wave form of it runs instead; GENERIC always runs the kernel with
- * 64-bit thresholds read from LDS (L <= 66) or L2.                           */
+ * one-wave form of it runs instead.  For L = 80, 96, 112, 128 the wide
+ * kernels read the 32-bit thresholds from global memory and keep only the
+ * histogram counters in LDS, again in a two-wave form while all its
+ * workgroups are resident at once and a one-wave form otherwise or with FAST.
+ * GENERIC always runs the kernel with 64-bit thresholds read from LDS
+ * (L <= 66) or L2.                                                         */
 #define MUCA_FLAG_GENERIC_KERNEL 0x10000u
 #define MUCA_FLAG_FAST_KERNEL 0x20000u
 
@@ -112,8 +116,9 @@ typedef struct muca_info {
     double chebyshev;       /* Eq. A.1: max |H/m - 1|, m = sum H / (N-1)     */
     double kernel_ms;       /* device time of the sweep launches (HIP events) */
     uint32_t kernel_launches; /* sweep kernel launches of the call           */
-    uint32_t kernel_variant;  /* 0: generic, 1: fast, 2: split, 3: wide
-                                 sweep kernel (the last of the call)         */
+    uint32_t kernel_variant;  /* 0: generic, 1: fast, 2: split, 3: wide,
+                                 4: wide two-wave sweep kernel (the last of
+                                 the call)                                   */
     uint32_t width;           /* bins from the lowest to the highest visited
                                  bin of H, inclusive (full range: N + 1)     */
     uint32_t reserved;

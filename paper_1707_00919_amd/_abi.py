@@ -24,7 +24,7 @@ STATUS_NAMES = {
 MUCA_MAX_L = 128
 MUCA_FLAG_GENERIC_KERNEL = 0x10000
 MUCA_FLAG_FAST_KERNEL = 0x20000
-KERNEL_GENERIC, KERNEL_FAST, KERNEL_SPLIT, KERNEL_WIDE = 0, 1, 2, 3
+KERNEL_GENERIC, KERNEL_FAST, KERNEL_SPLIT, KERNEL_WIDE, KERNEL_WIDE_SPLIT = 0, 1, 2, 3, 4
 
 
 class MucaParams(ctypes.Structure):

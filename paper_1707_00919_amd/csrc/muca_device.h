@@ -85,6 +85,13 @@ __host__ __device__ constexpr uint32_t split_lds_bytes(uint32_t L)
     return 28u * (L * L + 1u) + 2u * ((L % 4u == 0u ? 1u : 2u) * L / 4u) * (uint32_t)kWave * 16u;
 }
 
+// LDS bytes of one workgroup of the two-wave sweep for L > 64: the 32-bit
+// histogram counters (rounded up to 16 bytes) in front of the same ring.
+__host__ __device__ constexpr uint32_t wide_split_lds_bytes(uint32_t L)
+{
+    return (4u * (L * L + 1u) + 15u) / 16u * 16u + 2u * ((L % 4u == 0u ? 1u : 2u) * L / 4u) * (uint32_t)kWave * 16u;
+}
+
 // Waves (of 64 walkers each) per workgroup of the fast sweep.  The record
 // table is per workgroup; where it is so large that fewer than four
 // workgroups fit in a CU's LDS, several waves share one copy so that every
@@ -97,10 +104,18 @@ __host__ __device__ constexpr uint32_t fast_waves_per_group(uint32_t L)
 // The two-wave (split) form pays while every one of its workgroups is resident
 // at once and at most two share a CU (their producer waves then do not compete
 // with the chains); otherwise the one-wave form runs more chains at a time.
+inline bool prefer_two_waves(uint32_t lds_bytes, uint64_t blocks, uint32_t cus)
+{
+    const uint64_t per_cu = kLdsPerCu / lds_bytes;
+    return blocks <= (uint64_t)cus * (per_cu < 2u ? per_cu : 2u);
+}
 inline bool prefer_split(uint32_t L, uint64_t blocks, uint32_t cus)
 {
-    const uint64_t per_cu = kLdsPerCu / split_lds_bytes(L);
-    return blocks <= (uint64_t)cus * (per_cu < 2u ? per_cu : 2u);
+    return prefer_two_waves(split_lds_bytes(L), blocks, cus);
+}
+inline bool prefer_wide_split(uint32_t L, uint64_t blocks, uint32_t cus)
+{
+    return prefer_two_waves(wide_split_lds_bytes(L), blocks, cus);
 }
 
 // Largest number of recorded sweeps one launch may run without a 32-bit LDS
@@ -126,6 +141,9 @@ hipError_t launch_init(const InitArgs& a, hipStream_t s);
 // (32-byte records; valid when no reachable T is 0).
 bool wide_sweep_supported(uint32_t L);
 hipError_t launch_wide_sweep(uint32_t L, const FastSweepArgs& a, hipStream_t s);
+// The same tables with the random numbers on a second wave (two-wave form).
+bool wide_split_supported(uint32_t L);
+hipError_t launch_wide_split_sweep(uint32_t L, const FastSweepArgs& a, hipStream_t s);
 hipError_t launch_sweep(uint32_t L, const SweepArgs& a, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* p, size_t n, hipStream_t s);
 

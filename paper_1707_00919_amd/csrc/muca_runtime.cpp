@@ -430,11 +430,16 @@ int run_attempts(muca_instance* h, uint64_t therm, uint64_t recorded, bool updat
         return fail(h, MUCA_ERR_OVERFLOW, "attempt position would wrap");
 
     compute_thresholds(N, h->omega.data(), h->table5.data());
-    // kernel choice: 3 wide, 2 split, 1 fast, 0 generic (all give the same bits)
+    // kernel choice: 4 wide two-wave, 3 wide, 2 split, 1 fast, 0 generic (all
+    // give the same bits)
     uint32_t variant = 0;
     if (!(h->p.flags & MUCA_FLAG_GENERIC_KERNEL) && muca::wide_sweep_supported(h->L) &&
         fast_table(N, h->table5.data(), reinterpret_cast<uint32_t*>(h->h_table4), 8)) {
-        variant = 3;
+        // as for L <= 64: a second wave for the random numbers pays while every
+        // workgroup is resident at once
+        const bool two = !(h->p.flags & MUCA_FLAG_FAST_KERNEL) && muca::wide_split_supported(h->L) &&
+                         muca::prefer_wide_split(h->L, h->wpad / muca::kWave, (uint32_t)h->cus);
+        variant = two ? 4 : 3;
     } else if (!(h->p.flags & MUCA_FLAG_GENERIC_KERNEL) &&
         (muca::split_sweep_supported(h->L) || muca::fast_sweep_supported(h->L)) &&
         fast_table(N, h->table5.data(), reinterpret_cast<uint32_t*>(h->h_table4), 5)) {
@@ -479,7 +484,7 @@ int run_attempts(muca_instance* h, uint64_t therm, uint64_t recorded, bool updat
             a.site_begin = g.site_begin;
             a.site_end = g.site_end;
             a.rec_begin = g.rec_begin;
-            a.table_stride = variant == 3 ? 8u : (fast ? 5u : 0u);
+            a.table_stride = variant >= 3 ? 8u : (fast ? 5u : 0u);
             MUCA_HIP(h, muca::launch_sweep_range(a, h->stream), "partial sweep launch");
             ++launches;
             continue;
@@ -500,7 +505,8 @@ int run_attempts(muca_instance* h, uint64_t therm, uint64_t recorded, bool updat
                 a.nsweeps = n;
                 a.therm = th;
                 MUCA_HIP(h,
-                         variant == 3   ? muca::launch_wide_sweep(h->L, a, h->stream)
+                         variant == 4   ? muca::launch_wide_split_sweep(h->L, a, h->stream)
+                         : variant == 3 ? muca::launch_wide_sweep(h->L, a, h->stream)
                          : variant == 2 ? muca::launch_split_sweep(h->L, a, h->stream)
                                         : muca::launch_fast_sweep(h->L, a, h->stream),
                          "sweep launch");

@@ -1,5 +1,5 @@
 // muca_sweep_split.hip -- the multicanonical sweep with the random numbers and
-// the Metropolis chain on two different waves (gfx950, L <= 64).
+// the Metropolis chain on two different waves (gfx950).
 //
 // Each walker's chain is serial: an attempt's threshold depends on the energy
 // the previous attempt left behind (Sec. 2.2-2.3).  With 64 walkers per wave
@@ -13,12 +13,17 @@
 //    runs only the chain, reading four draws with one 16-byte LDS load.  One
 //    barrier per loop step hands a ring slot over.
 //  * The consumer's chain step (muca_chain.h) resolves attempt x while the two
-//    thresholds attempt x+1 can need are already on their way from LDS.
+//    thresholds attempt x+1 can need are already on their way.
 //
-// Per-bin LDS records are 28 bytes (7 words: the five thresholds S = T - 1 by
-// the number m of anti-aligned neighbours, the histogram counter, one pad
-// word): an odd word stride spreads the gathers of 64 lanes over all banks.
+// For L <= 64 the per-bin records live in LDS: 28 bytes (7 words: the five
+// thresholds S = T - 1 by the number m of anti-aligned neighbours, the
+// histogram counter, one pad word); an odd word stride spreads the gathers of
+// 64 lanes over all banks.  For L = 80..128 (the wide form) the records do not
+// fit: the chain reads the 32-byte threshold records from global memory through
+// the caches and LDS holds only the 32-bit counters in front of the ring.
 // The row bookkeeping (bond words, vertical fields) is in muca_rowbits.h.
+#include <type_traits>
+
 #include "muca_device.h"
 
 #include "muca_chain.h"
@@ -27,10 +32,14 @@
 namespace muca {
 namespace {
 
-template <int L>
+// LDS of one workgroup: the records (or, in the wide form, the counters
+// rounded up to 16 bytes) in front of two ring slots of one loop step each.
+template <int L, bool WIDE>
 struct SplitShape : ChainShape<L> {
-    static constexpr int SLOT_BYTES = ChainShape<L>::BLOCKS * kWave * 16;
-    static constexpr int LDS_BYTES = ChainShape<L>::REC_BYTES + 2 * SLOT_BYTES;
+    using C = ChainShape<L>;
+    static constexpr int FRONT_BYTES = WIDE ? (4 * (C::N + 1) + 15) / 16 * 16 : C::REC_BYTES;
+    static constexpr int SLOT_BYTES = C::BLOCKS * kWave * 16;
+    static constexpr int LDS_BYTES = FRONT_BYTES + 2 * SLOT_BYTES;
 };
 
 // The consumer's random words: one 16-byte load per block from the ring slot
@@ -55,16 +64,16 @@ struct RingDraws {
 };
 
 // Producer: the Philox words of every site of loop step s into ring slot s & 1.
-template <int L>
+template <int L, bool WIDE>
 __device__ __forceinline__ void produce_step(uint8_t* lds, uint32_t s, const FastSweepArgs& a,
                                              uint32_t walker, uint32_t lane)
 {
-    using S = SplitShape<L>;
+    using S = SplitShape<L, WIDE>;
     const uint32_t t = s / S::STEPS;
     const uint32_t y = (s - t * S::STEPS) * S::RPS;
     const uint64_t sweep = a.sweep0 + t;
     const uint32_t blk0 = (y * L) >> 2;
-    uint8_t* slot = lds + S::REC_BYTES + (s & 1u) * S::SLOT_BYTES;
+    uint8_t* slot = lds + S::FRONT_BYTES + (s & 1u) * S::SLOT_BYTES;
 #pragma unroll 2
     for (int b = 0; b < S::BLOCKS; ++b) {
         const Words4 r = philox10(blk0 + (uint32_t)b, (uint32_t)sweep, (uint32_t)(sweep >> 32), 0u,
@@ -74,65 +83,91 @@ __device__ __forceinline__ void produce_step(uint8_t* lds, uint32_t s, const Fas
     }
 }
 
-template <int L>
+template <int L, bool WIDE>
 __device__ __forceinline__ void sweep_split_kernel_body(const FastSweepArgs& a, uint32_t block)
 {
-    using S = SplitShape<L>;
+    using S = SplitShape<L, WIDE>;
+    using R = std::conditional_t<WIDE, GlobalRecords, LdsRecords>;
+    constexpr int N = S::N;
     static_assert(S::LDS_BYTES <= 160 * 1024, "records and ring must fit in LDS");
-    static_assert(S::LDS_BYTES == (int)split_lds_bytes(L), "LDS size formula");
+    static_assert(S::LDS_BYTES == (int)(WIDE ? wide_split_lds_bytes(L) : split_lds_bytes(L)), "LDS size formula");
     __shared__ __attribute__((aligned(16))) uint8_t lds[S::LDS_BYTES];
+    uint32_t* const counters = reinterpret_cast<uint32_t*>(lds);  // wide form
 
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const bool consumer = threadIdx.x < kWave;  // wave 0: chain; wave 1: random numbers
     const uint32_t w = block * kWave + lane;
     const uint32_t steps = a.nsweeps * (uint32_t)S::STEPS;
 
-    chain_records_fill<L>(lds, a.table, threadIdx.x, 2 * kWave);
+    if constexpr (WIDE) {
+        for (int k = threadIdx.x; k <= N; k += 2 * kWave)
+            counters[k] = 0u;
+    } else {
+        chain_records_fill<L>(lds, a.table, threadIdx.x, 2 * kWave);
+    }
     if (!consumer && steps > 0)
-        produce_step<L>(lds, 0u, a, w, lane);
+        produce_step<L, WIDE>(lds, 0u, a, w, lane);
     __syncthreads();
 
     uint32_t* const mine = a.spins + w;
     const size_t stride = a.wpad;
     ChainState<L> st;
     const uint32_t live = w < a.walkers ? 1u : 0u;
-    const LdsRecords recs{lds};
+    R recs;
+    if constexpr (WIDE)
+        recs = GlobalRecords{reinterpret_cast<const uint8_t*>(a.table), lds};
+    else
+        recs = LdsRecords{lds};
     if (consumer)
-        chain_load<L, LdsRecords>(st, mine, stride, a.energy[w]);
+        chain_load<L, R>(st, mine, stride, a.energy[w]);
 
     for (uint32_t s = 0; s < steps; ++s) {
         if (consumer) {
             const uint32_t t = s / S::STEPS;
             const int y = (int)(s - t * S::STEPS) * S::RPS;
             const uint32_t inc = t >= a.therm ? live : 0u;
-            RingDraws draws{lds, S::REC_BYTES + (s & 1u) * S::SLOT_BYTES, lane};
+            RingDraws draws{lds, S::FRONT_BYTES + (s & 1u) * S::SLOT_BYTES, lane};
             Words4 rn = draws.first();
             Words4 rc;
             chain_row<L, 0>(st, rc, rn, draws, recs, inc, mine, stride, y);
             if constexpr (S::RPS == 2)
                 chain_row<L, 1>(st, rc, rn, draws, recs, inc, mine, stride, y);
         } else if (s + 1 < steps) {
-            produce_step<L>(lds, s + 1, a, w, lane);
+            produce_step<L, WIDE>(lds, s + 1, a, w, lane);
         }
         __syncthreads();
     }
     if (consumer)
         a.energy[w] = chain_finish<L>(st, recs);
     __syncthreads();
-    chain_records_flush<L>(lds, a.hist, threadIdx.x, 2 * kWave);
+    if constexpr (WIDE) {
+        for (int k = threadIdx.x; k <= N; k += 2 * kWave) {
+            const uint32_t v = counters[k];
+            if (v)
+                atomicAdd(a.hist + k, (unsigned long long)v);
+        }
+    } else {
+        chain_records_flush<L>(lds, a.hist, threadIdx.x, 2 * kWave);
+    }
 }
 
 template <int L>
 __global__ __launch_bounds__(128) void sweep_split_kernel(FastSweepArgs a)
 {
-    sweep_split_kernel_body<L>(a, blockIdx.x);
+    sweep_split_kernel_body<L, false>(a, blockIdx.x);
+}
+
+template <int L>
+__global__ __launch_bounds__(128) void sweep_wide_split_kernel(FastSweepArgs a)
+{
+    sweep_split_kernel_body<L, true>(a, blockIdx.x);
 }
 
 template <int L>
 __global__ __launch_bounds__(128) void sweep_split_kernel_batch(const FastSweepArgs* args, const BatchItem* items)
 {
     const BatchItem it = items[blockIdx.x];
-    sweep_split_kernel_body<L>(args[it.member], it.block);
+    sweep_split_kernel_body<L, false>(args[it.member], it.block);
 }
 
 template <int L>
@@ -146,6 +181,13 @@ template <int L>
 hipError_t launch_split_L(const FastSweepArgs& a, hipStream_t s)
 {
     hipLaunchKernelGGL(sweep_split_kernel<L>, dim3(a.wpad / kWave), dim3(2 * kWave), 0, s, a);
+    return hipGetLastError();
+}
+
+template <int L>
+hipError_t launch_wide_split_L(const FastSweepArgs& a, hipStream_t s)
+{
+    hipLaunchKernelGGL(sweep_wide_split_kernel<L>, dim3(a.wpad / kWave), dim3(2 * kWave), 0, s, a);
     return hipGetLastError();
 }
 
@@ -177,6 +219,33 @@ hipError_t launch_split_sweep(uint32_t L, const FastSweepArgs& a, hipStream_t s)
     case LL:          \
         return launch_split_L<LL>(a, s);
         MUCA_SPLIT_L(MUCA_CASE)
+#undef MUCA_CASE
+    default:
+        return hipErrorInvalidValue;
+    }
+}
+
+#define MUCA_WIDE_SPLIT_L(X) X(80) X(96) X(112) X(128)
+
+bool wide_split_supported(uint32_t L)
+{
+    switch (L) {
+#define MUCA_CASE(LL) case LL:
+        MUCA_WIDE_SPLIT_L(MUCA_CASE)
+#undef MUCA_CASE
+        return true;
+    default:
+        return false;
+    }
+}
+
+hipError_t launch_wide_split_sweep(uint32_t L, const FastSweepArgs& a, hipStream_t s)
+{
+    switch (L) {
+#define MUCA_CASE(LL) \
+    case LL:          \
+        return launch_wide_split_L<LL>(a, s);
+        MUCA_WIDE_SPLIT_L(MUCA_CASE)
 #undef MUCA_CASE
     default:
         return hipErrorInvalidValue;

@@ -133,17 +133,19 @@ def test_kernel_variants_agree(L, W, seed):
         assert_state(s, o)
 
 
-@pytest.mark.parametrize("L,W,seed", [(80, 65, 31), (96, 130, 32), (112, 64, 33), (128, 200, 34)])
-def test_wide_kernel_agrees(L, W, seed):
-    # L > 64: the wide kernel (thresholds from global memory, counters in LDS)
-    # and the generic kernel against the oracle
+@pytest.mark.parametrize("L,W,seed,default", [(80, 65, 31, 4), (96, 130, 32, 4), (112, 64, 33, 4),
+                                              (128, 200, 34, 4), (96, 16448, 36, 3)])
+def test_wide_kernel_agrees(L, W, seed, default):
+    # L > 64: the wide kernels (thresholds from global memory, counters in
+    # LDS) in their two-wave form (chosen while every workgroup is resident at
+    # once) and one-wave form, and the generic kernel, against the oracle
     from paper_1707_00919_amd import _abi
     note("wide kernel L=%d W=%d seed=%d" % (L, W, seed))
     o = oracle.OracleMuca(L, W, seed)
     om = smooth_log_weights(L, seed + 100)
     o.set_log_weights(om)
     oi = o.iterate(1, 2)
-    for flags, variant in [(0, 3), (_abi.MUCA_FLAG_GENERIC_KERNEL, 0)]:
+    for flags, variant in [(0, default), (_abi.MUCA_FLAG_FAST_KERNEL, 3), (_abi.MUCA_FLAG_GENERIC_KERNEL, 0)]:
         s = Solver(L, W, seed, flags=flags)
         s.set_log_weights(om)
         si = s.iterate(1, 2)
