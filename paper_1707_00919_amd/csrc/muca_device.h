@@ -82,7 +82,7 @@ constexpr uint32_t kLdsPerCu = 160u * 1024u;
 __host__ __device__ constexpr uint32_t fast_lds_bytes(uint32_t L) { return 28u * (L * L + 1u); }
 __host__ __device__ constexpr uint32_t split_lds_bytes(uint32_t L)
 {
-    return 28u * (L * L + 1u) + 2u * ((L % 4u == 0u ? 1u : 2u) * L / 4u) * (uint32_t)kWave * 16u;
+    return (28u * (L * L + 1u) + 15u) / 16u * 16u + 2u * ((L % 4u == 0u ? 1u : 2u) * L / 4u) * (uint32_t)kWave * 16u;
 }
 
 // LDS bytes of one workgroup of the two-wave sweep for L > 64: the 32-bit

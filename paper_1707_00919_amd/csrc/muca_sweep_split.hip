@@ -32,12 +32,13 @@
 namespace muca {
 namespace {
 
-// LDS of one workgroup: the records (or, in the wide form, the counters
-// rounded up to 16 bytes) in front of two ring slots of one loop step each.
+// LDS of one workgroup: the records (or, in the wide form, the counters) in
+// front of two ring slots of one loop step each, which start on a 16-byte
+// boundary so that every 16-byte ring access is aligned.
 template <int L, bool WIDE>
 struct SplitShape : ChainShape<L> {
     using C = ChainShape<L>;
-    static constexpr int FRONT_BYTES = WIDE ? (4 * (C::N + 1) + 15) / 16 * 16 : C::REC_BYTES;
+    static constexpr int FRONT_BYTES = ((WIDE ? 4 * (C::N + 1) : C::REC_BYTES) + 15) / 16 * 16;
     static constexpr int SLOT_BYTES = C::BLOCKS * kWave * 16;
     static constexpr int LDS_BYTES = FRONT_BYTES + 2 * SLOT_BYTES;
 };
