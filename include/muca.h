@@ -87,12 +87,13 @@ typedef enum muca_status {
  * histogram counters in LDS, again in a two-wave form while all its
  * workgroups are resident at once and a one-wave form otherwise or with FAST.
  * GENERIC always runs the kernel with 64-bit thresholds read from LDS
- * (L <= 66) or L2.                                                         */
+ * (L <= 64) or L2.                                                         */
 #define MUCA_FLAG_GENERIC_KERNEL 0x10000u
 #define MUCA_FLAG_FAST_KERNEL 0x20000u
 
 typedef struct muca_params {
-    uint32_t L;       /* even, 4 <= L <= MUCA_MAX_L                          */
+    uint32_t L;       /* 4, 6, ..., 64 or 80, 96, 112, 128 (MUCA_MAX_L); the
+                         even sizes in between have no kernels built      */
     uint32_t walkers; /* number of independent walkers, >= 1 (Sec. 2.2)      */
     uint32_t seed;    /* first word of every walker's Philox key             */
     uint32_t flags;   /* MUCA_FLAG_*                                         */

@@ -49,7 +49,7 @@ def test_state_bytes_sizes(lib):
 
 def test_create_rejects_invalid_params_without_a_device(lib):
     h = ctypes.c_void_p()
-    for L, W in [(5, 64), (2, 64), (0, 64), (130, 64), (32, 0)]:
+    for L, W in [(5, 64), (2, 64), (0, 64), (130, 64), (66, 64), (70, 64), (126, 64), (32, 0)]:
         p = _abi.MucaParams(L, W, 1, 0)
         rc = lib.muca_create(ctypes.byref(p), None, None, 0, ctypes.byref(h))
         assert rc == _abi.MUCA_ERR_INVALID_ARG
