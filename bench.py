@@ -416,8 +416,10 @@ def bench_served(args):
 
 def bench_schedule(args):
     """The paper's iteration schedule (Sec. 3: Eq. 7 update counts, f_therm
-    = 30, growth 1.1, stop at d_k < 1e-4) at L = 32, 16384 walkers, then a
-    production run; time to converged weights and ln g accuracy."""
+    = 30, growth 1.1, stop at d_k < 1e-4 -- or at d_c < 0.05, App. A) at
+    L = 32, 16384 walkers, then a production run; time to converged weights,
+    ln g accuracy, and seed 1's d_k and d_c per iteration (the quantities of
+    the paper's f_therm study, App. A, for the f_therm given)."""
     import torch
     from paper_1707_00919_amd import Solver
     L, W = 32, 16384
@@ -427,8 +429,10 @@ def bench_schedule(args):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         s = Solver(L, W, seed)
-        ok, steps = s.run_schedule(max_iterations=1000)
+        ok, steps = s.run_schedule(max_iterations=1000, stop=args.schedule_stop, f_therm=args.f_therm)
         t_w = time.perf_counter() - t0
+        if seed == 1:
+            trace = [[st["kl_divergence"], st["chebyshev"]] for st in steps]
         s.production(10000, 10000)
         lng = s.log_dos(0)
         wall = time.perf_counter() - t0
@@ -450,7 +454,8 @@ def bench_schedule(args):
         "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
         "data": "synthetic",
         "config": {"workload": "paper_schedule_L32", "L": L, "walkers": W, "z": 2.25,
-                   "f_therm": 30, "growth": 1.1, "dk_flat": 1e-4, "production": [10000, 10000]},
+                   "f_therm": args.f_therm, "growth": 1.1, "stop": args.schedule_stop,
+                   "dk_flat": 1e-4, "dc_flat": 0.05, "production": [10000, 10000]},
         "ttcw_p50_s": nearest_rank([r["ttcw"] for r in runs], 50),
         "ttcw_p99_s": nearest_rank([r["ttcw"] for r in runs], 99),
         "iterations": [r["iterations"] for r in runs],
@@ -458,6 +463,7 @@ def bench_schedule(args):
         "converged": sum(r["ok"] for r in runs),
         "ln_g_max_abs_err": max(r["err"] for r in runs),
         "attempts_per_s": sum(r["attempts"] for r in runs) / wall,
+        "seed1_dk_dc_per_iteration": trace,
     }
     print(json.dumps(out), flush=True)
 
@@ -548,6 +554,10 @@ def main():
                              "served_poisson20", "paper_schedule_L32", "production_L32"],
                     help="the headline workload (default) or one of the batched, served "
                          "and paper-schedule workloads, each with its own JSON line")
+    ap.add_argument("--schedule-stop", choices=["kl", "chebyshev"], default="kl",
+                    help="paper_schedule_L32: stop at d_k < 1e-4 (Eq. 6) or d_c < 0.05 (App. A)")
+    ap.add_argument("--f-therm", type=int, default=30,
+                    help="paper_schedule_L32: thermalisation attempts per walker per bin of w")
     ap.add_argument("--serve-duration", type=float, default=60.0)
     ap.add_argument("--block-sweeps", type=int, default=1000)
     ap.add_argument("--cpu-seconds", type=float, default=20.0)

@@ -174,14 +174,18 @@ int muca_production_attempts(muca_instance* h, uint64_t therm_attempts, uint64_t
  * x = 6 w^z / walkers up to and including the first iteration with w = N + 1
  * and x grows by the factor `growth` in every later iteration; then Eq. 4.
  * From that first full-range iteration on, the run stops after the first
- * iteration whose d_k (muca_info.kl_divergence) is below dk_flat.  The
- * paper's values: z = 2.25, growth = 1.1, dk_flat = 1e-4, f_therm = 30,
- * w_min = 10.                                                               */
+ * iteration whose d_k (muca_info.kl_divergence) is below dk_flat -- or,
+ * with stop_rule MUCA_STOP_CHEBYSHEV, whose Chebyshev distance d_c
+ * (muca_info.chebyshev, App. A) is below dc_flat, the alternative the paper
+ * reports to stop at a comparable time.  The paper's values: z = 2.25,
+ * growth = 1.1, dk_flat = 1e-4 (dc_flat = 0.05), f_therm = 30, w_min = 10.  */
+#define MUCA_STOP_KL 0u
+#define MUCA_STOP_CHEBYSHEV 1u
 typedef struct muca_schedule {
-    double z, growth, dk_flat;
+    double z, growth, dk_flat, dc_flat;
     uint32_t f_therm, w_min;
     uint32_t max_iterations;  /* give up after this many (> 0)               */
-    uint32_t reserved;
+    uint32_t stop_rule;       /* MUCA_STOP_KL or MUCA_STOP_CHEBYSHEV         */
 } muca_schedule;
 
 typedef struct muca_schedule_step {

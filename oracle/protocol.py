@@ -14,7 +14,10 @@ bins):
   * the weights are updated by Eq. 4; from the first iteration whose w is
     the full range on, the run stops after the first iteration whose
     Kullback-Leibler divergence d_k (Eq. 6, P = H / sum H, Q uniform over
-    the reachable bins of the previous iteration's range) is below 10^-4.
+    the reachable bins of the previous iteration's range) is below 10^-4 --
+    or, with the alternative rule of App. A, whose Chebyshev distance
+    d_c = max |H / m - 1| over the reachable bins (m = sum H / their number)
+    is below 0.05.
 Readings where the text leaves room: the growth phase, once entered, is kept
 even if a later iteration covers a narrower range; the stop test waits for
 the full range, because before it Q need not cover the current histogram
@@ -24,9 +27,12 @@ import math
 
 
 def run_paper_schedule(o, z=2.25, f_therm=30, growth=1.1, dk_flat=1e-4, w_min=10,
-                       max_iterations=1000):
-    """Iterate the oracle instance ``o`` (an ``OracleMuca``) by the schedule.
-    Returns (converged, steps) with one dict per iteration."""
+                       max_iterations=1000, stop="kl", dc_flat=0.05):
+    """Iterate the oracle instance ``o`` (an ``OracleMuca``) by the schedule,
+    stopping on d_k < dk_flat (stop="kl") or d_c < dc_flat
+    (stop="chebyshev").  Returns (converged, steps) with one dict per
+    iteration."""
+    assert stop in ("kl", "chebyshev")
     x = None
     full = False
     steps = []
@@ -43,6 +49,7 @@ def run_paper_schedule(o, z=2.25, f_therm=30, growth=1.1, dk_flat=1e-4, w_min=10
         steps.append({"therm_attempts": n_therm, "update_attempts": n_updates, "width": w,
                       "covered": info["width"], "kl_divergence": info["kl_divergence"],
                       "chebyshev": info["chebyshev"], "flatness": info["flatness"]})
-        if full and info["kl_divergence"] < dk_flat:
+        d, below = (info["chebyshev"], dc_flat) if stop == "chebyshev" else (info["kl_divergence"], dk_flat)
+        if full and d < below:
             return True, steps
     return False, steps

@@ -53,8 +53,8 @@ _INT = ctypes.c_int
 
 class Schedule(ctypes.Structure):
     _fields_ = [("z", ctypes.c_double), ("growth", ctypes.c_double), ("dk_flat", ctypes.c_double),
-                ("f_therm", ctypes.c_uint32), ("w_min", ctypes.c_uint32),
-                ("max_iterations", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("dc_flat", ctypes.c_double), ("f_therm", ctypes.c_uint32), ("w_min", ctypes.c_uint32),
+                ("max_iterations", ctypes.c_uint32), ("stop_rule", ctypes.c_uint32)]
 
 
 class ScheduleStep(ctypes.Structure):
@@ -148,6 +148,8 @@ PROTOTYPES = {
 MUCA_BATCH_SKIP = 0
 MUCA_BATCH_ITERATE = 1
 MUCA_BATCH_PRODUCTION = 2
+MUCA_STOP_KL = 0
+MUCA_STOP_CHEBYSHEV = 1
 MUCA_BATCH_GRAPH = 0x1
 MUCA_BATCH_AUTOTUNE = 0x2
 

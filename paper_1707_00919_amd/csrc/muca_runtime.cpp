@@ -697,8 +697,13 @@ int muca_run_schedule(muca_instance* h, const muca_schedule* sc, muca_schedule_s
         *iterations = 0;
     if (int rc = check_live(h))
         return rc;
-    if (!sc || !(sc->z > 0.0) || !(sc->growth >= 1.0) || !(sc->dk_flat > 0.0) || sc->max_iterations == 0)
-        return fail(h, MUCA_ERR_INVALID_ARG, "schedule needs z > 0, growth >= 1, dk_flat > 0, max_iterations > 0");
+    if (!sc || !(sc->z > 0.0) || !(sc->growth >= 1.0) || sc->max_iterations == 0 ||
+        sc->stop_rule > MUCA_STOP_CHEBYSHEV)
+        return fail(h, MUCA_ERR_INVALID_ARG, "schedule needs z > 0, growth >= 1, max_iterations > 0, a known stop rule");
+    const bool chebyshev = sc->stop_rule == MUCA_STOP_CHEBYSHEV;
+    const double stop_below = chebyshev ? sc->dc_flat : sc->dk_flat;
+    if (!(stop_below > 0.0))
+        return fail(h, MUCA_ERR_INVALID_ARG, "the stop rule's threshold must be > 0");
     if (steps == nullptr && max_steps != 0)
         return fail(h, MUCA_ERR_INVALID_ARG, "steps is NULL");
     const uint32_t N = h->N;
@@ -735,7 +740,7 @@ int muca_run_schedule(muca_instance* h, const muca_schedule* sc, muca_schedule_s
             st.covered = info.width;
             steps[it] = st;
         }
-        if (full && info.kl_divergence < sc->dk_flat)
+        if (full && (chebyshev ? info.chebyshev : info.kl_divergence) < stop_below)
             return MUCA_OK;
     }
     return fail(h, MUCA_ERR_NOT_CONVERGED, "the schedule reached max_iterations");

@@ -112,10 +112,14 @@ class Solver:
         return info.as_dict()
 
     def run_schedule(self, z=2.25, growth=1.1, dk_flat=1e-4, f_therm=30, w_min=10,
-                     max_iterations=1000):
-        """The paper's iteration schedule (Sec. 3) to its stop rule.
+                     max_iterations=1000, stop="kl", dc_flat=0.05):
+        """The paper's iteration schedule (Sec. 3) to its stop rule: d_k <
+        dk_flat (Eq. 6), or with stop="chebyshev" d_c < dc_flat (App. A).
         Returns (converged, [step dicts])."""
-        sc = _abi.Schedule(z, growth, dk_flat, f_therm, w_min, max_iterations, 0)
+        rules = {"kl": _abi.MUCA_STOP_KL, "chebyshev": _abi.MUCA_STOP_CHEBYSHEV}
+        if stop not in rules:
+            raise ValueError("stop must be 'kl' or 'chebyshev'")
+        sc = _abi.Schedule(z, growth, dk_flat, dc_flat, f_therm, w_min, max_iterations, rules[stop])
         steps = (_abi.ScheduleStep * max_iterations)()
         n = ctypes.c_uint32()
         rc = self._lib.muca_run_schedule(self._h, ctypes.byref(sc), steps, max_iterations,

@@ -41,6 +41,28 @@ def test_schedule_converges_to_exact_dos(golden_dir):
     assert np.max(np.abs(ln_g[m] - exact[m])) < 0.02
 
 
+def test_chebyshev_stop_rule_converges_to_exact_dos(golden_dir):
+    # App. A's alternative stop rule, d_c < 0.05 from the first full-range
+    # iteration on: it ends the schedule, every earlier full-range iteration
+    # had d_c >= 0.05, and the weights it leaves give ln g within 0.02
+    L, W = 4, 64
+    o = oracle.OracleMuca(L, W, 2)
+    ok, steps = run_paper_schedule(o, max_iterations=400, stop="chebyshev")
+    assert ok
+    full = [i for i, s in enumerate(steps) if s["width"] == L * L + 1]
+    assert full and steps[-1]["chebyshev"] < 0.05
+    assert all(s["chebyshev"] >= 0.05 for s in steps[full[0]:-1])
+    # d_c is the largest relative deviation from the flat mean over the
+    # reachable bins of the last histogram
+    h = o.hist.astype(float)
+    m = oracle.reachable_mask(L * L)
+    mean = h[m].sum() / m.sum()
+    assert abs(np.max(np.abs(h[m] / mean - 1.0)) - steps[-1]["chebyshev"]) < 1e-12
+    o.production(200, 20000)
+    exact = golden_ln_g(golden_dir, L)
+    assert np.max(np.abs(o.log_dos(0)[m] - exact[m])) < 0.02
+
+
 def test_schedule_bookkeeping():
     L, W = 6, 40
     o = oracle.OracleMuca(L, W, 3)
