@@ -303,13 +303,15 @@ typedef struct muca_batch muca_batch;
                                      sweep counts and kernel forms) is unchanged;
                                      rounds that need several launches per member
                                      run without the graph                     */
-#define MUCA_BATCH_AUTOTUNE 0x2u  /* time three launch shapes on the first three
+#define MUCA_BATCH_AUTOTUNE 0x2u  /* time four launch shapes on the first four
                                      rounds and keep the fastest: the two-wave
                                      form, the one-wave form with its default
-                                     walkers per workgroup, and the one-wave form
+                                     walkers per workgroup, the one-wave form
                                      with 256 walkers (four waves) sharing each
-                                     threshold table (results do not depend on
-                                     the choice)                               */
+                                     threshold table, and the default form with
+                                     the histograms merged twice per round (two
+                                     launches); results do not depend on the
+                                     choice                                    */
 
 /* Group count live instances.  members[] stay owned by the caller and must
  * outlive the batch; they are not to be called while a round runs, and all

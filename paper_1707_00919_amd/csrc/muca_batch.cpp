@@ -50,11 +50,14 @@ struct Group {
     uint32_t nitems = 0;
 };
 
-// The autotuner's choices for members that can run the LDS-record kernels:
+// The autotuner's choices: for members that can run the LDS-record kernels
 // the two-wave form, the one-wave form with its default wave groups, or the
-// one-wave form with four waves (256 walkers) sharing each table.
-constexpr int kChoices = 3;
-constexpr int kTwoWave = 0, kOneWaveDefault = 1, kOneWaveFour = 2;
+// one-wave form with four waves (256 walkers) sharing each table; and the
+// histogram-merge cadence -- the default form with the round's sweeps cut
+// into two launches, so that every workgroup's LDS counters are merged into
+// the global histogram twice per round instead of once.
+constexpr int kChoices = 4;
+constexpr int kTwoWave = 0, kOneWaveDefault = 1, kOneWaveFour = 2, kTwoMerges = 3;
 
 }  // namespace
 
@@ -95,7 +98,7 @@ struct muca_batch {
     std::string host_err;
     // autotuner: attempts/ms of the two-wave and one-wave forms
     uint32_t round = 0;
-    double tuned_rate[kChoices] = {0.0, 0.0, 0.0};
+    double tuned_rate[kChoices] = {0.0, 0.0, 0.0, 0.0};
     int tuned_form = -1;
     int choice = kTwoWave;  // of the submitted round
     std::string err;
@@ -488,16 +491,18 @@ int muca_batch_submit(muca_batch* b, const uint32_t* mode, const uint32_t* therm
     b->choice = two_wave ? kTwoWave : kOneWaveDefault;
     if (b->flags & MUCA_BATCH_AUTOTUNE)
         b->choice = b->tuned_form >= 0 ? b->tuned_form : (int)(b->round % kChoices);
+    // the kernel form of the choice (the merge-cadence choice keeps the default form)
+    const int shape = b->choice == kTwoMerges ? (two_wave ? kTwoWave : kOneWaveDefault) : b->choice;
     std::vector<uint32_t> waves(count, 1u);
     for (uint32_t i = 0; i < count; ++i) {
         const uint32_t L = b->m[i]->L;
         if (form[i] == kFast) {
-            const bool want_fast = (b->m[i]->p.flags & MUCA_FLAG_FAST_KERNEL) != 0 || b->choice != kTwoWave;
+            const bool want_fast = (b->m[i]->p.flags & MUCA_FLAG_FAST_KERNEL) != 0 || shape != kTwoWave;
             if (muca::split_sweep_supported(L) && !(want_fast && muca::fast_sweep_supported(L))) {
                 form[i] = kSplit;
             } else {
                 form[i] = kFast;
-                waves[i] = b->choice == kOneWaveFour ? 4u : muca::fast_waves_per_group(L);
+                waves[i] = shape == kOneWaveFour ? 4u : muca::fast_waves_per_group(L);
             }
         }
         // a launch stays below 2^32 counts per LDS counter of a workgroup
@@ -546,6 +551,8 @@ int muca_batch_submit(muca_batch* b, const uint32_t* mode, const uint32_t* therm
     uint64_t longest = 0;
     for (uint32_t i = 0; i < count; ++i)
         longest = std::max(longest, total[i]);
+    if (b->choice == kTwoMerges && longest > 1)
+        chunk = (uint32_t)std::min<uint64_t>(chunk, (longest + 1) / 2);
     b->pending = true;
     auto dev_fail = [&](const char* what, hipError_t e) {
         b->err = std::string(what) + ": " + hipGetErrorName(e) + " (" + hipGetErrorString(e) + ")";
