@@ -212,6 +212,21 @@ def cpu_full_solve(wl, iter_cap, seed=1):
     return {"seed": seed, "iterations": it, "ttcw_s": t_w, "cores": threads, "kind": "oracle"}
 
 
+def host_cpu():
+    """The host CPU the oracle ran on: model name and the logical CPUs this
+    process may use."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "usable_cpus": len(os.sched_getaffinity(0)), "nproc": os.cpu_count()}
+
+
 def cpu_baseline(wl, ln_g, sweeps, warm, nthreads=0):
     import oracle
     L, W = wl["L"], wl["walkers"]
@@ -227,6 +242,7 @@ def cpu_baseline(wl, ln_g, sweeps, warm, nthreads=0):
         "unit": "attempts/s",
         "cores": threads,
         "kind": "oracle",
+        "host": host_cpu(),
         "sample": "L=%d, %d walkers, %d sweeps after %d warm-up sweeps at exact weights "
                   "omega = -ln g (%.2e attempts, %.1f s)" % (L, W, sweeps, warm, info["attempts"], dt),
     }
