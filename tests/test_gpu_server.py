@@ -73,6 +73,14 @@ def test_served_equals_alone(batch_flags):
     assert st["completed"] == len(REQUESTS) and st["active"] == 0 and st["queued"] == 0
     assert st["resident_bytes"] == 0
     assert saw_queue and max_resident <= cap
+    # continuous batching, not a queue: requests of different L were resident
+    # at the same time, and a request submitted after the first five was
+    # admitted while one of them was still running
+    span = [(out[t][0]["t_admit"], out[t][0]["t_done"]) for t in tickets]
+    overlap = lambda a, b: span[a][0] < span[b][1] and span[b][0] < span[a][1]
+    n = len(REQUESTS)
+    assert any(overlap(i, j) and REQUESTS[i][0] != REQUESTS[j][0] for i in range(n) for j in range(i + 1, n))
+    assert any(overlap(i, j) for i in range(5) for j in range(5, n))
     for t, (L, W, seed) in zip(tickets, REQUESTS):
         res, lng = out[t]
         it, flat, ref = solo(L, W, seed)
