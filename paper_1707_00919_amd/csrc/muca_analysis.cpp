@@ -14,7 +14,7 @@
 #include <vector>
 
 #include "muca.h"
-#include "muca_internal.h"
+#include "muca_host_math.h"
 
 namespace {
 

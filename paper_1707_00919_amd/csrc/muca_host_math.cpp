@@ -1,0 +1,221 @@
+// muca_host_math.cpp -- the host arithmetic of libmuca that needs no device:
+// acceptance thresholds from the log weights and their kernel encodings, the
+// histogram statistics, ln g, and the cut of a call into sweep segments.
+// Kept free of HIP so that it can also be built alone (with the sanitizers,
+// in the CPU tests).
+#include "muca_host_math.h"
+
+#include <algorithm>
+#include <cmath>
+#include <limits>
+
+namespace muca_host {
+
+// Acceptance thresholds (Sec. 2.3 acceptance min(1, exp[omega(E') - omega(E)])
+// as an integer bound on a uint32 draw): T[k*5+d], k' = k + d - 2.
+void compute_thresholds(uint32_t N, const double* om, uint64_t* t5)
+{
+    const uint64_t always = (uint64_t)1 << 32;
+    for (uint32_t k = 0; k <= N; ++k) {
+        for (int d = 0; d < 5; ++d) {
+            const long kp = (long)k + d - 2;
+            uint64_t t = 0;
+            if (kp >= 0 && kp <= (long)N) {
+                const double diff = om[kp] - om[k];
+                if (om[kp] >= om[k])
+                    t = always;
+                else
+                    t = (uint64_t)std::floor(std::ldexp(std::exp(diff), 32));
+            }
+            t5[(size_t)k * 5 + d] = t;
+        }
+    }
+}
+
+// Device table: the four energy-changing moves per bin, ordered by the number
+// m of anti-aligned neighbours (m = 0, 1, 3, 4 <-> d = 4, 3, 1, 0).
+void device_table(uint32_t N, const uint64_t* t5, uint64_t* t4)
+{
+    static const int kDofSlot[4] = {4, 3, 1, 0};
+    for (uint32_t k = 0; k <= N; ++k)
+        for (int s = 0; s < 4; ++s)
+            t4[(size_t)k * 4 + s] = t5[(size_t)k * 5 + kDofSlot[s]];
+}
+
+// Fast-kernel table: S = T - 1 as uint32 for every move out of bin k, indexed
+// by the count m = 0..4 of anti-aligned neighbours (d = 4 - m).  A move can be
+// proposed only between energies some configuration has: never to a target
+// outside 0..N, and never from or to the forbidden bins 1 and N-1 (no
+// configuration has E = -(2N-4) or 2N-4, Sec. 3).  Those entries are never
+// read and get 0.  Returns false when a move that can be proposed has T = 0:
+// r <= T - 1 cannot express "never", so the generic kernel must run.
+bool fast_table(uint32_t N, const uint64_t* t5, uint32_t* f, uint32_t stride)
+{
+    for (uint32_t k = 0; k <= N; ++k) {
+        for (uint32_t m = 5; m < stride; ++m)
+            f[(size_t)k * stride + m] = 0u;
+        for (int m = 0; m < 5; ++m) {
+            const long kp = (long)k + 2 - m;
+            const uint64_t t = t5[(size_t)k * 5 + (4 - m)];
+            if (kp < 0 || kp > (long)N || k == 1 || k == N - 1 || kp == 1 || kp == (long)N - 1) {
+                f[(size_t)k * stride + m] = 0u;
+                continue;
+            }
+            if (t == 0)
+                return false;
+            f[(size_t)k * stride + m] = (uint32_t)(t - 1);
+        }
+    }
+    return true;
+}
+
+static bool reachable(uint32_t N, uint32_t k) { return k != 1 && k != N - 1; }
+
+double flatness_of(uint32_t N, const uint64_t* H)
+{
+    uint64_t sum = 0, mn = std::numeric_limits<uint64_t>::max();
+    for (uint32_t k = 0; k <= N; ++k) {
+        if (!reachable(N, k))
+            continue;
+        sum += H[k];
+        if (H[k] < mn)
+            mn = H[k];
+    }
+    if (sum == 0)
+        return 0.0;
+    const double mean = (double)sum / (double)(N - 1);
+    return (double)mn / mean;
+}
+
+double chebyshev_of(uint32_t N, const uint64_t* H)
+{
+    uint64_t sum = 0;
+    for (uint32_t k = 0; k <= N; ++k)
+        if (reachable(N, k))
+            sum += H[k];
+    if (sum == 0)
+        return 0.0;
+    const double m = (double)sum / (double)(N - 1);
+    double worst = 0.0;
+    for (uint32_t k = 0; k <= N; ++k) {
+        if (!reachable(N, k))
+            continue;
+        const double dev = std::fabs((double)H[k] / m - 1.0);
+        if (dev > worst)
+            worst = dev;
+    }
+    return worst;
+}
+
+double kl_of(uint32_t N, const uint64_t* H, int reach_prev)
+{
+    uint64_t sum = 0;
+    for (uint32_t k = 0; k <= N; ++k)
+        sum += H[k];
+    if (sum == 0)
+        return 0.0;
+    const double w = (double)(reach_prev > 10 ? reach_prev : 10);
+    double dk = 0.0;
+    for (uint32_t k = 0; k <= N; ++k) {
+        if (H[k] == 0)
+            continue;
+        const double p = (double)H[k] / (double)sum;
+        dk += p * std::log(p * w);
+    }
+    return dk;
+}
+
+int reach_of(uint32_t N, const uint64_t* H)
+{
+    int lo = -1, hi = -1;
+    for (uint32_t k = 0; k <= N; ++k)
+        if (H[k] > 0) {
+            if (lo < 0)
+                lo = (int)k;
+            hi = (int)k;
+        }
+    int n = 0;
+    for (int k = lo; lo >= 0 && k <= hi; ++k)
+        n += (k != 1 && k != (int)N - 1) ? 1 : 0;
+    return n;
+}
+
+int width_of(uint32_t N, const uint64_t* H)
+{
+    int lo = -1, hi = -1;
+    for (uint32_t k = 0; k <= N; ++k) {
+        if (H[k] > 0) {
+            if (lo < 0)
+                lo = (int)k;
+            hi = (int)k;
+        }
+    }
+    return lo < 0 ? 0 : hi - lo + 1;
+}
+
+int log_dos_of(uint32_t N, const uint64_t* H, const double* omega, int normalization, double* out)
+{
+    double mx = -INFINITY;
+    for (uint32_t k = 0; k <= N; ++k) {
+        if (k != 1 && k != N - 1 && H[k] > 0) {
+            out[k] = std::log((double)H[k]) - omega[k];
+            if (out[k] > mx)
+                mx = out[k];
+        } else {
+            out[k] = -INFINITY;
+        }
+    }
+    double c;
+    if (normalization == 0) {
+        if (H[0] == 0)
+            return 1;
+        c = std::log(2.0) - out[0];
+    } else {
+        if (mx == -INFINITY)
+            return 2;
+        double s = 0.0;
+        for (uint32_t k = 0; k <= N; ++k)
+            if (out[k] != -INFINITY)
+                s += std::exp(out[k] - mx);
+        c = (double)N * std::log(2.0) - (mx + std::log(s));
+    }
+    for (uint32_t k = 0; k <= N; ++k)
+        if (out[k] != -INFINITY)
+            out[k] += c;
+    return 0;
+}
+
+// Cuts the attempts [pos0, pos0 + therm + recorded) -- recording from
+// pos0 + therm on -- into whole-sweep runs for the sweep kernels and partial
+// sweeps for the range kernel.  A sweep that holds the start of recording is
+// run as a partial sweep unless recording starts at its first site.
+std::vector<Segment> segments_of(uint64_t N, uint64_t pos0, uint64_t therm, uint64_t recorded)
+{
+    std::vector<Segment> out;
+    const uint64_t rec = pos0 + therm, end = rec + recorded;
+    uint64_t p = pos0;
+    while (p < end) {
+        const uint64_t sweep = p / N, base = sweep * N;
+        const uint64_t sweep_end = base + N;
+        const bool partial = p != base || end < sweep_end || (rec > p && rec < sweep_end);
+        if (partial) {
+            const uint64_t e = std::min(end, sweep_end);
+            const uint64_t rb = std::min(std::max(rec, p), e);
+            out.push_back(Segment{sweep, 0, 0, (uint32_t)(p - base), (uint32_t)(e - base),
+                                  (uint32_t)(rb - base)});
+            p = e;
+            continue;
+        }
+        // whole sweeps up to the end, or up to the sweep holding the start of
+        // recording when that start is not on a sweep boundary
+        uint64_t n = (end - p) / N;
+        if (rec > p && (rec - p) % N != 0)
+            n = std::min(n, (rec - p) / N);
+        const uint64_t th = rec > p ? std::min(n, (rec - p) / N) : 0;
+        out.push_back(Segment{sweep, n, th, 0, 0, 0});
+        p += n * N;
+    }
+    return out;
+}
+
+}  // namespace muca_host

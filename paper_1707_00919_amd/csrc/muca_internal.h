@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "muca.h"
+#include "muca_host_math.h"
 
 namespace muca_host {
 
@@ -22,26 +23,6 @@ struct Layout {
     size_t total;
 };
 
-// Acceptance thresholds T[k*5+d] from the log weights (IEEE double, libm exp).
-void compute_thresholds(uint32_t N, const double* om, uint64_t* t5);
-// Generic-kernel table: uint64 thresholds of the four energy-changing moves.
-void device_table(uint32_t N, const uint64_t* t5, uint64_t* t4);
-// Table of the fast, split and wide kernels: uint32 S = T - 1 at f[k*stride + m]
-// by the number m of anti-aligned neighbours (stride 5, or 8 for the wide
-// kernel's 32-byte records, the rest zero); false if a move that can be
-// proposed has T = 0.
-bool fast_table(uint32_t N, const uint64_t* t5, uint32_t* f, uint32_t stride);
-double flatness_of(uint32_t N, const uint64_t* H);
-double chebyshev_of(uint32_t N, const uint64_t* H);
-// ln g[k] = ln H[k] - omega[k] + c on reachable bins with H > 0, -inf
-// elsewhere; normalization 0: ln g[0] = ln 2, 1: sum exp(ln g) = 2^N.
-// Returns 0, or 1 (ground-state bin empty) / 2 (histogram empty).
-int log_dos_of(uint32_t N, const uint64_t* H, const double* omega, int normalization, double* out);
-// Eq. 6 with Q uniform over max(reach_prev, 10) bins.
-double kl_of(uint32_t N, const uint64_t* H, int reach_prev);
-// Reachable bins (not 1 or N-1) between the lowest and highest visited bin.
-int reach_of(uint32_t N, const uint64_t* H);
-int width_of(uint32_t N, const uint64_t* H);
 
 }  // namespace muca_host
 
