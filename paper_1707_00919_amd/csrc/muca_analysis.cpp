@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <cmath>
 #include <limits>
+#include <new>
 #include <vector>
 
 #include "muca.h"
@@ -73,8 +74,8 @@ double jk_error(const std::vector<double>& loo)
 
 extern "C" {
 
-int muca_jackknife_log_dos(uint32_t L, uint32_t blocks, const uint64_t* block_hists,
-                           const double* omega, int normalization, double* ln_g, double* ln_g_err)
+static int muca_jackknife_log_dos_impl(uint32_t L, uint32_t blocks, const uint64_t* block_hists,
+                                       const double* omega, int normalization, double* ln_g, double* ln_g_err)
 {
     if (!args_ok(L, blocks, block_hists, omega) || !ln_g || (normalization != 0 && normalization != 1))
         return MUCA_ERR_INVALID_ARG;
@@ -114,9 +115,22 @@ int muca_jackknife_log_dos(uint32_t L, uint32_t blocks, const uint64_t* block_hi
     return MUCA_OK;
 }
 
-int muca_canonical(uint32_t L, uint32_t blocks, const uint64_t* block_hists, const double* omega,
-                   uint32_t n_beta, const double* betas, double* energy, double* energy_err,
-                   double* specific_heat, double* specific_heat_err)
+// No C++ exception leaves the C ABI: a failed host allocation is reported.
+int muca_jackknife_log_dos(uint32_t L, uint32_t blocks, const uint64_t* block_hists,
+                           const double* omega, int normalization, double* ln_g, double* ln_g_err)
+{
+    try {
+        return muca_jackknife_log_dos_impl(L, blocks, block_hists, omega, normalization, ln_g, ln_g_err);
+    } catch (const std::bad_alloc&) {
+        return MUCA_ERR_OUT_OF_MEMORY;
+    } catch (...) {
+        return MUCA_ERR_STATE;
+    }
+}
+
+static int muca_canonical_impl(uint32_t L, uint32_t blocks, const uint64_t* block_hists, const double* omega,
+                               uint32_t n_beta, const double* betas, double* energy, double* energy_err,
+                               double* specific_heat, double* specific_heat_err)
 {
     if (!args_ok(L, blocks, block_hists, omega) || (n_beta && (!betas || !energy || !specific_heat)))
         return MUCA_ERR_INVALID_ARG;
@@ -155,6 +169,21 @@ int muca_canonical(uint32_t L, uint32_t blocks, const uint64_t* block_hists, con
             specific_heat_err[j] = ce;
     }
     return MUCA_OK;
+}
+
+// No C++ exception leaves the C ABI: a failed host allocation is reported.
+int muca_canonical(uint32_t L, uint32_t blocks, const uint64_t* block_hists, const double* omega,
+                   uint32_t n_beta, const double* betas, double* energy, double* energy_err,
+                   double* specific_heat, double* specific_heat_err)
+{
+    try {
+        return muca_canonical_impl(L, blocks, block_hists, omega, n_beta, betas, energy, energy_err, specific_heat,
+                                   specific_heat_err);
+    } catch (const std::bad_alloc&) {
+        return MUCA_ERR_OUT_OF_MEMORY;
+    } catch (...) {
+        return MUCA_ERR_STATE;
+    }
 }
 
 }  // extern "C"

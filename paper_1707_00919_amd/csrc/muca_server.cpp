@@ -414,7 +414,7 @@ int muca_server_create(const muca_server_config* cfg, muca_server** out)
     return MUCA_OK;
 }
 
-int muca_server_submit(muca_server* s, const muca_request* q, uint64_t* ticket)
+static int muca_server_submit_impl(muca_server* s, const muca_request* q, uint64_t* ticket)
 {
     if (!s || !q || !ticket)
         return MUCA_ERR_INVALID_ARG;
@@ -427,13 +427,31 @@ int muca_server_submit(muca_server* s, const muca_request* q, uint64_t* ticket)
     r->ticket = s->next_ticket++;
     r->q = *q;
     r->t_submit = now_s(s);
-    *ticket = r->ticket;
-    s->queue.push_back(r.get());
-    s->requests[r->ticket] = std::move(r);
+    Request* raw = r.get();
+    s->requests[raw->ticket] = std::move(r);
+    try {
+        s->queue.push_back(raw);
+    } catch (...) {
+        s->requests.erase(raw->ticket);  // the queue never saw it
+        throw;
+    }
+    *ticket = raw->ticket;
     return MUCA_OK;
 }
 
-int muca_server_progress(muca_server* s, uint32_t* events)
+// No C++ exception leaves the C ABI: a failed host allocation is reported.
+int muca_server_submit(muca_server* s, const muca_request* q, uint64_t* ticket)
+{
+    try {
+        return muca_server_submit_impl(s, q, ticket);
+    } catch (const std::bad_alloc&) {
+        return sfail(s, MUCA_ERR_OUT_OF_MEMORY, "host allocation failed");
+    } catch (...) {
+        return sfail(s, MUCA_ERR_STATE, "unexpected host exception");
+    }
+}
+
+static int muca_server_progress_impl(muca_server* s, uint32_t* events)
 {
     if (!s)
         return MUCA_ERR_INVALID_ARG;
@@ -480,6 +498,18 @@ int muca_server_progress(muca_server* s, uint32_t* events)
     if (events)
         *events = ev;
     return MUCA_OK;
+}
+
+// No C++ exception leaves the C ABI: a failed host allocation is reported.
+int muca_server_progress(muca_server* s, uint32_t* events)
+{
+    try {
+        return muca_server_progress_impl(s, events);
+    } catch (const std::bad_alloc&) {
+        return sfail(s, MUCA_ERR_OUT_OF_MEMORY, "host allocation failed");
+    } catch (...) {
+        return sfail(s, MUCA_ERR_STATE, "unexpected host exception");
+    }
 }
 
 int muca_server_take(muca_server* s, uint64_t ticket, muca_result* res, double* ln_g, size_t n)
