@@ -410,8 +410,8 @@ int poison_round(muca_batch* b, const std::string& why)
 
 }  // namespace
 
-int muca_batch_submit(muca_batch* b, const uint32_t* mode, const uint32_t* therm,
-                      const uint32_t* sweeps)
+static int muca_batch_submit_impl(muca_batch* b, const uint32_t* mode, const uint32_t* therm,
+                                  const uint32_t* sweeps)
 {
     if (!b)
         return MUCA_ERR_INVALID_ARG;
@@ -661,6 +661,26 @@ int muca_batch_submit(muca_batch* b, const uint32_t* mode, const uint32_t* therm
     if ((e = hipEventRecord(b->ev_done, b->stream)) != hipSuccess)
         return dev_fail("hipEventRecord", e);
     return MUCA_OK;
+}
+
+// No C++ exception leaves the C ABI: a failed host allocation while a round
+// is set up is reported, and a round it interrupted poisons its members.
+int muca_batch_submit(muca_batch* b, const uint32_t* mode, const uint32_t* therm,
+                      const uint32_t* sweeps)
+{
+    int code = MUCA_ERR_STATE;
+    try {
+        return muca_batch_submit_impl(b, mode, therm, sweeps);
+    } catch (const std::bad_alloc&) {
+        code = MUCA_ERR_OUT_OF_MEMORY;
+    } catch (...) {
+    }
+    // a round that had started: let its device work end, then poison its members
+    if (b->pending) {
+        (void)hipStreamSynchronize(b->stream);
+        poison_round(b, "host exception while the round was set up");
+    }
+    return bfail(b, code, code == MUCA_ERR_OUT_OF_MEMORY ? "host allocation failed" : "unexpected host exception");
 }
 
 int muca_batch_query(muca_batch* b)

@@ -212,6 +212,12 @@ int run_attempts(muca_instance* h, uint64_t therm, uint64_t recorded, bool updat
     if (h->position + total < h->position)
         return fail(h, MUCA_ERR_OVERFLOW, "attempt position would wrap");
 
+    std::vector<muca_host::Segment> segments;
+    try {
+        segments = muca_host::segments_of(N, h->position, therm, recorded);
+    } catch (const std::bad_alloc&) {
+        return fail(h, MUCA_ERR_OUT_OF_MEMORY, "host allocation failed");
+    }
     compute_thresholds(N, h->omega.data(), h->table5.data());
     // kernel choice: 4 wide two-wave, 3 wide, 2 split, 1 fast, 0 generic (all
     // give the same bits)
@@ -252,7 +258,7 @@ int run_attempts(muca_instance* h, uint64_t therm, uint64_t recorded, bool updat
         chunk = cap;
     uint32_t launches = 0;
     MUCA_HIP(h, hipEventRecord(h->ev_start, h->stream), "hipEventRecord");
-    for (const muca_host::Segment& g : muca_host::segments_of(N, h->position, therm, recorded)) {
+    for (const muca_host::Segment& g : segments) {
         if (g.n == 0) {
             muca::RangeArgs a{};
             a.spins = h->d_spins;
