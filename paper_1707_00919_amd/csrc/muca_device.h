@@ -77,7 +77,8 @@ inline uint32_t padded_walkers(uint32_t walkers) { return (walkers + kWave - 1) 
 constexpr uint32_t kLdsPerCu = 160u * 1024u;
 
 // LDS bytes of one workgroup of the fast sweep (a 28-byte record per energy
-// bin) and of the split sweep (the records plus a two-slot ring of Philox
+// bin) and of the split sweep (the records, rounded up to 16 bytes so that
+// the ring's 16-byte accesses are aligned, plus a two-slot ring of Philox
 // words, one loop step of 64 walkers per slot).
 __host__ __device__ constexpr uint32_t fast_lds_bytes(uint32_t L) { return 28u * (L * L + 1u); }
 __host__ __device__ constexpr uint32_t split_lds_bytes(uint32_t L)

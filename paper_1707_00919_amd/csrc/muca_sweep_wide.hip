@@ -8,8 +8,11 @@
 // anti-aligned neighbours -- read from global memory through the caches (the
 // table, 512 KiB at L = 128, stays in L2), and only the 32-bit histogram
 // counters in LDS (64 KiB + 4 B at L = 128).  One wave per 64 walkers,
-// Philox4x32-10 computed in place.  Used when no reachable threshold is 0;
-// otherwise the generic kernel with 64-bit thresholds runs.
+// Philox4x32-10 computed in place.  Used when no reachable threshold is 0
+// (otherwise the generic kernel with 64-bit thresholds runs) and when there
+// are more workgroups than fit on the device at once, two per CU at most; with
+// fewer, the two-wave form of muca_sweep_split.hip (Philox on its own wave)
+// runs the same chain faster.
 #include "muca_device.h"
 
 #include "muca_chain.h"
