@@ -13,6 +13,11 @@ Contents
   * ``exact_dos``      -- exact density of states of the periodic L x L Ising
                           model: brute force, transfer matrix, and Kaufman's
                           closed form (the ground truth named in Sec. 3).
+  * ``protocol``       -- the paper's weight-iteration schedule (Sec. 3, Eq. 7;
+                          stop rules of Eq. 6 and App. A) driving OracleMuca.
+  * ``analysis``       -- jackknife errors over production blocks and canonical
+                          averages by reweighting (Sec. 2.1, Sec. 3.3), with
+                          brute-force and transfer-matrix references.
 """
 import ctypes
 import os
