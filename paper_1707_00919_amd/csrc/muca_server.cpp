@@ -47,61 +47,7 @@ namespace {
 
 thread_local std::string g_server_error;
 
-constexpr size_t kArenaAlign = 256;
-
-// First-fit allocator over [0, size) with coalescing of free neighbours.
-class Arena {
-public:
-    void reset(size_t size)
-    {
-        free_.clear();
-        if (size)
-            free_[0] = size;
-        size_ = size;
-        used_ = 0;
-    }
-    bool alloc(size_t n, size_t* off)
-    {
-        n = (n + kArenaAlign - 1) / kArenaAlign * kArenaAlign;
-        for (auto it = free_.begin(); it != free_.end(); ++it) {
-            if (it->second >= n) {
-                *off = it->first;
-                const size_t rest = it->second - n;
-                const size_t at = it->first + n;
-                free_.erase(it);
-                if (rest)
-                    free_[at] = rest;
-                used_ += n;
-                return true;
-            }
-        }
-        return false;
-    }
-    void release(size_t off, size_t n)
-    {
-        n = (n + kArenaAlign - 1) / kArenaAlign * kArenaAlign;
-        used_ -= n;
-        auto next = free_.lower_bound(off);
-        if (next != free_.end() && off + n == next->first) {
-            n += next->second;
-            next = free_.erase(next);
-        }
-        if (next != free_.begin()) {
-            auto prev = std::prev(next);
-            if (prev->first + prev->second == off) {
-                prev->second += n;
-                return;
-            }
-        }
-        free_[off] = n;
-    }
-    size_t used() const { return used_; }
-    size_t size() const { return size_; }
-
-private:
-    std::map<size_t, size_t> free_;  // offset -> length
-    size_t size_ = 0, used_ = 0;
-};
+using muca_host::Arena;
 
 enum Phase : uint32_t { kQueued = 0, kIterating = 1, kProducing = 2, kDone = 3 };
 

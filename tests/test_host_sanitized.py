@@ -1,13 +1,17 @@
-"""The library's host arithmetic (csrc/muca_host_math.cpp: thresholds and their
-kernel encodings, flatness, Chebyshev distance, KL divergence, covered ranges,
-ln g, the cut of a call into sweep segments; csrc/muca_analysis.cpp: jackknife
-and canonical reweighting) built alone with AddressSanitizer and
+"""The library's host arithmetic built alone with AddressSanitizer and
 UndefinedBehaviourSanitizer and run on seeded inputs, with its results checked
-against the oracle.  No device is involved: these sources include no HIP.
+against the oracle or against definitions.  No device is involved: these
+sources include no HIP.
 
-The segment cut is pinned by its definition: expanded attempt by attempt it
-must cover exactly the attempts of the call, in order, whole-sweep runs must
-start on sweep boundaries, and attempt p is recorded iff p >= pos0 + therm."""
+* csrc/muca_host_math.cpp: thresholds and their kernel encodings, flatness,
+  Chebyshev distance, KL divergence, covered ranges and ln g (against the
+  oracle); the cut of a call into sweep segments (attempt by attempt it must
+  cover exactly the attempts of the call, in order, and attempt p is recorded
+  iff p >= pos0 + therm); the serving form's arena (offset for offset the same
+  as first fit with coalescing written out from its definition, live ranges
+  disjoint and inside the arena).
+* csrc/muca_analysis.cpp: jackknife and canonical reweighting (against the
+  oracle)."""
 import os
 import shutil
 import struct
@@ -72,6 +76,32 @@ int main() {
     wr1((int32_t)muca_canonical(L, blocks, bh.data(), om.data(), nbeta, betas.data(), e.data(), ee.data(),
                                 c.data(), ce.data()));
     wr(e.data(), nbeta); wr(ee.data(), nbeta); wr(c.data(), nbeta); wr(ce.data(), nbeta);
+    // arena: a sequence of allocations and releases (of earlier allocations)
+    uint64_t arena_hdr[2];
+    if (fread(arena_hdr, 8, 2, stdin) != 2) return 3;
+    std::vector<uint64_t> ops;
+    rd(ops, 2 * (size_t)arena_hdr[0]);
+    muca_host::Arena arena;
+    arena.reset(arena_hdr[1]);
+    std::vector<uint64_t> offs, sizes;
+    for (uint64_t i = 0; i < arena_hdr[0]; ++i) {
+        if (ops[2 * i] == 0) {
+            size_t off = 0;
+            const bool ok = arena.alloc(ops[2 * i + 1], &off);
+            offs.push_back(ok ? off : ~0ull);
+            sizes.push_back(ops[2 * i + 1]);
+            const uint64_t o[2] = {ok ? 1ull : 0ull, ok ? (uint64_t)off : 0ull};
+            wr(o, 2);
+        } else {
+            const size_t j = ops[2 * i + 1];
+            const bool held = offs[j] != ~0ull;  // releasing a failed allocation is a no-op
+            if (held)
+                arena.release(offs[j], sizes[j]);
+            const uint64_t o[2] = {held ? 2ull : 3ull, 0ull};
+            wr(o, 2);
+        }
+        wr1((uint64_t)arena.used());
+    }
     for (uint32_t i = 0; i < ncut; ++i) {
         const auto segs = muca_host::segments_of(N, cuts[3 * i], cuts[3 * i + 1], cuts[3 * i + 2]);
         wr1((uint32_t)segs.size());
@@ -121,12 +151,72 @@ class Reader:
         return self.take(dtype, 1)[0]
 
 
-def run_case(exe, L, om, H, blocks, betas, reach_prev):
+def arena_ops(seed, n=400):
+    """A seeded mix of allocations (sizes 1 byte .. 40 KiB) and releases of
+    earlier ones, as (kind, arg) pairs: kind 0 allocates arg bytes, kind 1
+    releases allocation number arg (a no-op if that allocation failed)."""
+    rng = np.random.default_rng(seed)
+    ops, live, k = [], [], 0
+    for _ in range(n):
+        if live and rng.random() < 0.45:
+            ops.append((1, live.pop(int(rng.integers(0, len(live))))))
+        else:
+            ops.append((0, int(rng.integers(1, 40 * 1024))))
+            live.append(k)
+            k += 1
+    return ops
+
+
+def model_arena(size, ops):
+    """First fit with coalescing, written from its definition: sizes round
+    up to 256 bytes; an allocation takes the start of the lowest-addressed
+    free range that holds it; a release returns its range and merges it with
+    free neighbours.  Returns per op (status, offset, bytes in use); status
+    1 allocated, 0 no room, 2 released, 3 nothing to release."""
+    free = [[0, size]] if size else []
+    out, allocs, used = [], [], 0
+    for kind, a in ops:
+        if kind == 0:
+            n = -(-a // 256) * 256
+            hit = next((f for f in free if f[1] >= n), None)
+            if hit is None:
+                allocs.append(None)
+                out.append((0, 0, used))
+                continue
+            off = hit[0]
+            hit[0] += n
+            hit[1] -= n
+            free = [f for f in free if f[1] > 0]
+            used += n
+            allocs.append((off, n))
+            out.append((1, off, used))
+        else:
+            if allocs[a] is None:  # that allocation failed: nothing to release
+                out.append((3, 0, used))
+                continue
+            off, n = allocs[a]
+            used -= n
+            free.append([off, n])
+            free.sort()
+            merged = []
+            for f in free:
+                if merged and merged[-1][0] + merged[-1][1] == f[0]:
+                    merged[-1][1] += f[1]
+                else:
+                    merged.append(f)
+            free = merged
+            out.append((2, 0, used))
+    return out
+
+
+def run_case(exe, L, om, H, blocks, betas, reach_prev, arena=(0, [])):
     N = L * L
     inp = struct.pack("<5I", L, len(blocks), len(betas), len(CUTS), reach_prev)
     inp += np.asarray(om, np.float64).tobytes() + np.asarray(H, np.uint64).tobytes()
     inp += np.asarray(blocks, np.uint64).tobytes() + np.asarray(betas, np.float64).tobytes()
     inp += np.asarray(CUTS, np.uint64).tobytes()
+    size, ops = arena
+    inp += struct.pack("<2Q", len(ops), size) + np.asarray(ops, np.uint64).reshape(-1).tobytes()
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1")
     r = subprocess.run([exe], input=inp, capture_output=True, env=env, timeout=120)
     assert r.returncode == 0, r.stderr.decode(errors="replace")[-2000:]
@@ -148,6 +238,7 @@ def run_case(exe, L, om, H, blocks, betas, reach_prev):
     nb = len(betas)
     out["e"], out["e_err"] = rd.take(np.float64, nb), rd.take(np.float64, nb)
     out["c"], out["c_err"] = rd.take(np.float64, nb), rd.take(np.float64, nb)
+    out["arena"] = [tuple(int(x) for x in rd.take(np.uint64, 2)) + (int(rd.one(np.uint64)),) for _ in ops]
     segs = []
     for _ in CUTS:
         n = rd.one(np.uint32)
@@ -190,7 +281,26 @@ def test_host_math_under_sanitizers_matches_oracle(driver, L, seed, kind):
     om, H, blocks = make_case(L, seed, kind)
     betas = [0.2, 0.4406868, 0.7]
     reach_prev = oracle.reachable_width(H) if kind != "random" else 3
-    out = run_case(driver, L, om, H, blocks, betas, reach_prev)
+    arena_size = 1 << 18 if seed % 2 else (1 << 18) + 4096 + 17  # not a multiple of 256 too
+    ops = arena_ops(seed)
+    out = run_case(driver, L, om, H, blocks, betas, reach_prev, (arena_size, ops))
+
+    # the serving form's arena: exactly first fit with coalescing, and the
+    # live ranges never overlap or leave the arena
+    assert out["arena"] == model_arena(arena_size, ops)
+    live = {}
+    k = 0
+    for (kind, a), (st, off, _) in zip(ops, out["arena"]):
+        if kind == 0:
+            if st == 1:
+                n = -(-a // 256) * 256
+                assert off % 256 == 0 and off + n <= arena_size
+                assert all(off + n <= o or o + m <= off for o, m in live.values())
+                live[k] = (off, n)
+            k += 1
+        else:
+            live.pop(a, None)
+    assert any(st == 0 for st, _, _ in out["arena"]) and any(st == 2 for st, _, _ in out["arena"])
 
     t5 = oracle.thresholds(N, om)
     np.testing.assert_array_equal(out["t5"], t5.reshape(-1))
