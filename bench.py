@@ -593,8 +593,8 @@ def main():
                     help="short sweep + calibration copy for rocprofv3 counter runs")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: the method's walkers and histogram live on a "
-              "single device in this build (--gpus %d requested)" % args.gpus, file=sys.stderr)
+        print("bench.py runs on one GPU only: the walkers and the histogram of an instance live on a "
+              "single device (--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
     import torch
