@@ -74,13 +74,15 @@ def test_served_equals_alone(batch_flags):
     assert st["resident_bytes"] == 0
     assert saw_queue and max_resident <= cap
     # continuous batching, not a queue: requests of different L were resident
-    # at the same time, and a request submitted after the first five was
-    # admitted while one of them was still running
-    span = [(out[t][0]["t_admit"], out[t][0]["t_done"]) for t in tickets]
-    overlap = lambda a, b: span[a][0] < span[b][1] and span[b][0] < span[a][1]
+    # at the same time, and a request admitted only after another had finished
+    # (it waited for room) joined while a third, admitted before it, still ran
+    res = [out[t][0] for t in tickets]
+    overlap = lambda a, b: res[a]["t_admit"] < res[b]["t_done"] and res[b]["t_admit"] < res[a]["t_done"]
     n = len(REQUESTS)
     assert any(overlap(i, j) and REQUESTS[i][0] != REQUESTS[j][0] for i in range(n) for j in range(i + 1, n))
-    assert any(overlap(i, j) for i in range(5) for j in range(5, n))
+    first_done = min(r["t_done"] for r in res)
+    assert any(res[j]["t_admit"] >= first_done and res[i]["t_admit"] < res[j]["t_admit"] < res[i]["t_done"]
+               for i in range(n) for j in range(n) if i != j)
     for t, (L, W, seed) in zip(tickets, REQUESTS):
         res, lng = out[t]
         it, flat, ref = solo(L, W, seed)
