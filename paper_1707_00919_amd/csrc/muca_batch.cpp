@@ -40,7 +40,7 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 thread_local std::string g_batch_error;
 
 // kernel forms, as in muca_info::kernel_variant
-constexpr uint32_t kGeneric = 0, kFast = 1, kSplit = 2, kWide = 3;
+constexpr uint32_t kGeneric = 0, kFast = 1, kSplit = 2, kWide = 3, kWideSplit = 4;
 
 struct Group {
     uint32_t L = 0;
@@ -200,6 +200,8 @@ int enqueue_round(muca_batch* b, size_t stage_used, const std::vector<Group>& gr
         hipError_t e;
         if (G.form == kSplit)
             e = muca::launch_split_batch(G.L, fargs, items + G.first_item, G.nitems, s);
+        else if (G.form == kWideSplit)
+            e = muca::launch_wide_split_batch(G.L, fargs, items + G.first_item, G.nitems, s);
         else if (G.form == kWide)
             e = muca::launch_wide_batch(G.L, fargs, items + G.first_item, G.nitems, s);
         else if (G.form == kFast)
@@ -483,10 +485,17 @@ static int muca_batch_submit_impl(muca_batch* b, const uint32_t* mode, const uin
     // two-wave form while all of the batch's two-wave workgroups fit on the
     // device at once, at most two per CU (LDS shares weighted by each L)
     double lds_share = 0.0;
-    for (uint32_t i = 0; i < count; ++i)
-        if (form[i] == kFast && muca::split_sweep_supported(b->m[i]->L))
+    for (uint32_t i = 0; i < count; ++i) {
+        const uint32_t L = b->m[i]->L;
+        uint32_t bytes = 0;
+        if (form[i] == kFast && muca::split_sweep_supported(L))
+            bytes = muca::split_lds_bytes(L);
+        else if (form[i] == kWide && muca::wide_split_supported(L))
+            bytes = muca::wide_split_lds_bytes(L);
+        if (bytes)
             lds_share += (double)(b->m[i]->wpad / muca::kWave) *
-                         std::max(0.5, 1.0 / (double)(muca::kLdsPerCu / muca::split_lds_bytes(b->m[i]->L)));
+                         std::max(0.5, 1.0 / (double)(muca::kLdsPerCu / bytes));
+    }
     const bool two_wave = active_blocks <= 2u * (uint32_t)b->cus && lds_share <= (double)b->cus;
     b->choice = two_wave ? kTwoWave : kOneWaveDefault;
     if (b->flags & MUCA_BATCH_AUTOTUNE)
@@ -496,6 +505,9 @@ static int muca_batch_submit_impl(muca_batch* b, const uint32_t* mode, const uin
     std::vector<uint32_t> waves(count, 1u);
     for (uint32_t i = 0; i < count; ++i) {
         const uint32_t L = b->m[i]->L;
+        if (form[i] == kWide && shape == kTwoWave && !(b->m[i]->p.flags & MUCA_FLAG_FAST_KERNEL) &&
+            muca::wide_split_supported(L))
+            form[i] = kWideSplit;  // the same tables, Philox on a second wave
         if (form[i] == kFast) {
             const bool want_fast = (b->m[i]->p.flags & MUCA_FLAG_FAST_KERNEL) != 0 || shape != kTwoWave;
             if (muca::split_sweep_supported(L) && !(want_fast && muca::fast_sweep_supported(L))) {

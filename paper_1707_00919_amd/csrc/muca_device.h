@@ -175,5 +175,7 @@ hipError_t launch_wide_batch(uint32_t L, const FastSweepArgs* args, const BatchI
                              hipStream_t s);
 hipError_t launch_split_batch(uint32_t L, const FastSweepArgs* args, const BatchItem* items,
                               uint32_t nitems, hipStream_t s);
+hipError_t launch_wide_split_batch(uint32_t L, const FastSweepArgs* args, const BatchItem* items,
+                                   uint32_t nitems, hipStream_t s);
 
 }  // namespace muca

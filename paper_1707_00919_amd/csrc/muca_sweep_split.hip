@@ -172,9 +172,24 @@ __global__ __launch_bounds__(128) void sweep_split_kernel_batch(const FastSweepA
 }
 
 template <int L>
+__global__ __launch_bounds__(128) void sweep_wide_split_kernel_batch(const FastSweepArgs* args,
+                                                                     const BatchItem* items)
+{
+    const BatchItem it = items[blockIdx.x];
+    sweep_split_kernel_body<L, true>(args[it.member], it.block);
+}
+
+template <int L>
 hipError_t launch_split_L_batch_L(const FastSweepArgs* args, const BatchItem* items, uint32_t n, hipStream_t s)
 {
     hipLaunchKernelGGL(sweep_split_kernel_batch<L>, dim3(n), dim3(2 * kWave), 0, s, args, items);
+    return hipGetLastError();
+}
+
+template <int L>
+hipError_t launch_wide_split_L_batch(const FastSweepArgs* args, const BatchItem* items, uint32_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(sweep_wide_split_kernel_batch<L>, dim3(n), dim3(2 * kWave), 0, s, args, items);
     return hipGetLastError();
 }
 
@@ -246,6 +261,22 @@ hipError_t launch_wide_split_sweep(uint32_t L, const FastSweepArgs& a, hipStream
 #define MUCA_CASE(LL) \
     case LL:          \
         return launch_wide_split_L<LL>(a, s);
+        MUCA_WIDE_SPLIT_L(MUCA_CASE)
+#undef MUCA_CASE
+    default:
+        return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_wide_split_batch(uint32_t L, const FastSweepArgs* args, const BatchItem* items, uint32_t nitems,
+                                   hipStream_t s)
+{
+    if (nitems == 0)
+        return hipSuccess;
+    switch (L) {
+#define MUCA_CASE(LL) \
+    case LL:          \
+        return launch_wide_split_L_batch<LL>(args, items, nitems, s);
         MUCA_WIDE_SPLIT_L(MUCA_CASE)
 #undef MUCA_CASE
     default:

@@ -69,8 +69,11 @@ def test_batch_matches_solo(flags):
     solo = make(SHAPES)
     grouped = make(SHAPES)
     batch = Batch(grouped, flags=flags)
+    wide = SHAPES.index((96, 65, 9))
+    wide_forms = set()
     for modes, therm, sweeps in ROUNDS + ROUNDS[:1]:
         infos = batch.run(modes, therm, sweeps)
+        wide_forms.add(infos[wide]["kernel_variant"])
         for i, s in enumerate(solo):
             if modes[i] == 1:
                 si = s.iterate(therm[i], sweeps[i])
@@ -83,6 +86,9 @@ def test_batch_matches_solo(flags):
             assert infos[i]["sweep_counter"] == si["sweep_counter"]
     for a, b in zip(solo, grouped):
         same(a, b)
+    # the L = 96 member ran the two-wave wide form, and with the autotuner
+    # (which also tries the one-wave shapes) the one-wave wide form as well
+    assert wide_forms == ({3, 4} if flags & 2 else {4})
     batch.close()
 
 
@@ -242,7 +248,7 @@ def test_batch_member_with_zero_threshold_runs_generic():
         b.set_log_weights(om)
     batch = Batch(grouped)
     infos = batch.run([2, 1, 1], [1, 0, 1], [2, 3, 2])
-    assert infos[0]["kernel_variant"] == 0 and infos[2]["kernel_variant"] == 3
+    assert infos[0]["kernel_variant"] == 0 and infos[2]["kernel_variant"] == 4  # L = 96: wide, two waves
     solo[0].production(1, 2)
     solo[1].iterate(0, 3)
     solo[2].iterate(1, 2)
