@@ -48,6 +48,8 @@ class Solver:
         ws = None
         if use_torch and nbytes:
             import torch
+            if not torch.cuda.is_available():
+                raise MucaError(_abi.MUCA_ERR_DEVICE, "no GPU is visible to torch (this library runs on the GPU only)")
             dev = torch.device(device if device is not None else "cuda")
             with torch.cuda.device(dev):
                 self._workspace = torch.empty(nbytes, dtype=torch.uint8, device=dev)

@@ -109,3 +109,15 @@ def test_library_and_torch_share_one_hip_runtime():
     out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, timeout=300)
     assert out.returncode == 0, out.stderr
     assert out.stdout.strip().splitlines()[-1] == "1"
+
+
+def test_solver_without_a_gpu_fails_loudly():
+    """No CPU fallback: without a visible GPU the product path raises."""
+    import torch
+    if torch.cuda.device_count() > 0:
+        pytest.skip("a GPU is visible here")
+    from paper_1707_00919_amd import MucaError, Solver
+    for use_torch in (True, False):
+        with pytest.raises(MucaError) as e:
+            Solver(4, 64, 1, use_torch=use_torch)
+        assert e.value.code == _abi.MUCA_ERR_DEVICE
