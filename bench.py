@@ -375,7 +375,7 @@ def bench_served(args):
     from paper_1707_00919_amd import Server, Solver
     from muca_inputs import SERVE_REQUEST as Q, serving_requests
     reqs = serving_requests(duration=args.serve_duration)
-    srv = Server(64 << 30, max_active_walkers=args.serve_max_walkers, batch_flags=1)
+    srv = Server(64 << 30, max_active_walkers=args.serve_max_walkers, batch_flags=1, policy=args.serve_policy)
     t0 = time.perf_counter()
     tickets = {}
     nxt = 0
@@ -435,6 +435,7 @@ def bench_served(args):
                    "arrival_rate_per_s": 20.0, "arrival_window_s": args.serve_duration,
                    "L": [16, 24, 32, 48, 64], "walkers": [1024, 16384],
                    "mem_cap_bytes": 64 << 30, "max_active_walkers": args.serve_max_walkers,
+                   "admission": args.serve_policy,
                    **Q},
         "latency_p50_s": nearest_rank(lat, 50), "latency_p99_s": nearest_rank(lat, 99),
         "ttcw_p50_s": nearest_rank(ttcw, 50), "ttcw_p99_s": nearest_rank(ttcw, 99),
@@ -603,6 +604,8 @@ def main():
     ap.add_argument("--block-sweeps", type=int, default=1000)
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--serve-max-walkers", type=int, default=1 << 19)
+    ap.add_argument("--serve-policy", choices=["fifo", "smallest-first"], default="fifo",
+                    help="served_poisson20: admission order of queued requests")
     ap.add_argument("--serve-solo-sample", type=int, default=24,
                     help="solve this many of the first requests alone, one per launch, "
                          "for the comparison rate")

@@ -378,8 +378,13 @@ typedef struct muca_server_config {
     uint64_t max_active_walkers;  /* admit while the admitted walkers stay
                                      within this (0: no limit)               */
     uint32_t batch_flags;         /* MUCA_BATCH_* for the lanes               */
-    uint32_t reserved;
+    uint32_t policy;              /* MUCA_SERVE_FIFO: admit in arrival order;
+                                     MUCA_SERVE_SMALLEST_FIRST: admit the
+                                     queued request of least estimated work
+                                     (walkers * N^2) first                   */
 } muca_server_config;
+#define MUCA_SERVE_FIFO 0u
+#define MUCA_SERVE_SMALLEST_FIRST 1u
 
 typedef struct muca_request {
     double min_flatness;          /* stop iterating at flatness >= this      */

@@ -69,7 +69,7 @@ class ScheduleStep(ctypes.Structure):
 
 class ServerConfig(ctypes.Structure):
     _fields_ = [("mem_cap_bytes", ctypes.c_uint64), ("max_active_walkers", ctypes.c_uint64),
-                ("batch_flags", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("batch_flags", ctypes.c_uint32), ("policy", ctypes.c_uint32)]
 
 
 class Request(ctypes.Structure):
@@ -148,6 +148,8 @@ PROTOTYPES = {
 MUCA_BATCH_SKIP = 0
 MUCA_BATCH_ITERATE = 1
 MUCA_BATCH_PRODUCTION = 2
+MUCA_SERVE_FIFO = 0
+MUCA_SERVE_SMALLEST_FIRST = 1
 MUCA_STOP_KL = 0
 MUCA_STOP_CHEBYSHEV = 1
 MUCA_BATCH_GRAPH = 0x1

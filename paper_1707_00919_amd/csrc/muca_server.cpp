@@ -168,10 +168,31 @@ void retire(muca_server* s, Request* r, int status, const std::string& why)
     ++s->completed;
 }
 
-// Admits queued requests in arrival order while the head fits.
+// Estimated work of a solve: walkers * N attempts per sweep, times the
+// iterations to a flat histogram, which grow about like N.
+double work_of(const Request* r)
+{
+    const double n = (double)r->q.L * r->q.L;
+    return (double)r->q.walkers * n * n;
+}
+
+// Admits queued requests while the next one fits: in arrival order, or with
+// MUCA_SERVE_SMALLEST_FIRST the one of least estimated work first (ties in
+// arrival order).
 int admit(muca_server* s)
 {
     while (!s->queue.empty()) {
+        if (s->cfg.policy == MUCA_SERVE_SMALLEST_FIRST) {
+            auto best = s->queue.begin();
+            for (auto it = s->queue.begin(); it != s->queue.end(); ++it)
+                if (work_of(*it) < work_of(*best))
+                    best = it;
+            if (best != s->queue.begin()) {
+                Request* b = *best;
+                s->queue.erase(best);
+                s->queue.push_front(b);
+            }
+        }
         Request* r = s->queue.front();
         if (s->cfg.max_active_walkers && s->active_walkers > 0 &&
             s->active_walkers + r->q.walkers > s->cfg.max_active_walkers)
@@ -341,6 +362,8 @@ int muca_server_create(const muca_server_config* cfg, muca_server** out)
         return sfail(nullptr, MUCA_ERR_INVALID_ARG, "a memory cap is required");
     if (cfg->batch_flags & ~(uint32_t)(MUCA_BATCH_GRAPH | MUCA_BATCH_AUTOTUNE))
         return sfail(nullptr, MUCA_ERR_INVALID_ARG, "unknown batch flag");
+    if (cfg->policy > MUCA_SERVE_SMALLEST_FIRST)
+        return sfail(nullptr, MUCA_ERR_INVALID_ARG, "unknown admission policy");
     muca_server* s = new (std::nothrow) muca_server();
     if (!s)
         return sfail(nullptr, MUCA_ERR_OUT_OF_MEMORY, "host allocation failed");

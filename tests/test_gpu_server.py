@@ -51,12 +51,12 @@ def solo(L, W, seed):
     return it, flat, lng
 
 
-@pytest.mark.parametrize("batch_flags", [0, 3])
-def test_served_equals_alone(batch_flags):
+@pytest.mark.parametrize("batch_flags,policy", [(0, "fifo"), (3, "fifo"), (3, "smallest-first")])
+def test_served_equals_alone(batch_flags, policy):
     from paper_1707_00919_amd import Server, state_bytes
-    note("server mix, batch_flags=%d" % batch_flags)
+    note("server mix, batch_flags=%d, policy=%s" % (batch_flags, policy))
     cap = sum(sorted(state_bytes(L, W) for L, W, _ in REQUESTS)[-3:]) + 4096
-    srv = Server(cap, batch_flags=batch_flags)
+    srv = Server(cap, batch_flags=batch_flags, policy=policy)
     tickets = [srv.submit(L, W, s, **KW) for L, W, s in REQUESTS[:5]]
     max_resident = 0
     saw_queue = False
