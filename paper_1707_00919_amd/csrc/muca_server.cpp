@@ -7,9 +7,10 @@
 // request resident on the device -- lattices, energies, histogram, weights --
 // until it is done, and runs the admitted requests together:
 //
-//   queue    requests wait in arrival order; the head is admitted when its
-//            device state (muca_state_bytes) fits in the free part of the
-//            server's arena and the walker budget allows it;
+//   queue    requests wait in arrival order (or, with the smallest-first
+//            policy, the one of least estimated work goes next); the next one
+//            is admitted when its device state (muca_state_bytes) fits in the
+//            free part of the server's arena and the walker budget allows it;
 //   lanes    admitted requests are grouped by L; each lane is one batch
 //            (muca_batch) on its own stream, so lanes of different L run at
 //            the same time and each lane starts its next round as soon as its
