@@ -1,7 +1,9 @@
 """Pins for the oracle's run of the paper's iteration schedule (Sec. 3).
 
-The paper prints no worked example of the schedule, so its update counts are
-pinned by what they must achieve and by bookkeeping:
+The paper prints no worked example of the schedule.  Its update counts are
+pinned by Eq. 7 worked by hand (the literal counts at the end of this file,
+for two walker counts, before and after the full range is reached), by what
+they must achieve and by bookkeeping:
   * on the 4 x 4 lattice the schedule stops by its own rule (d_k < 10^-4
     after the full range is covered) and a production run at the weights it
     leaves gives ln g within 0.02 of exhaustive enumeration;
@@ -89,3 +91,41 @@ def test_schedule_counts_follow_w_then_grow():
     for a, b in zip(grow, grow[1:]):
         # b - 1 = floor(1.1 x), a - 1 = floor(x): |b - 1 - 1.1 (a - 1)| < 1.1
         assert abs((b - 1) - 1.1 * (a - 1)) < 1.1 + 1e-9
+
+
+# Eq. 7 worked by hand for the 6 x 6 lattice (N + 1 = 37 bins, so the full
+# range is w = 37).  x = 6 w^2.25 / W, N_updates = floor(x) + 1:
+#   W = 64: w = 10: 10^2.25 = 177.8279..., x = 6 * 177.8279 / 64 = 16.671 -> 17
+#           w = 16: 16^2.25 = 2^9 = 512, x = 3072 / 64 = 48 exactly   -> 49
+#           w = 37: 37^2.25 = 3376.40..., x = 316.537                 -> 317
+#   W = 40: w = 10: x = 26.674 -> 27; w = 16: x = 76.8 -> 77; w = 37: x = 506.460 -> 507
+# (w^2.25 = exp(2.25 ln w); the values for the other w were worked the same way,
+# to 50 digits, and are listed below).  After the first full-range iteration x
+# grows by 1.1 per iteration:
+#   W = 64: 316.537 * 1.1 = 348.191 -> 349, 383.010 -> 384, 421.311 -> 422, 463.443 -> 464
+#   W = 40: 506.460 * 1.1 = 557.106 -> 558, 612.817 -> 613, 674.098 -> 675, 741.508 -> 742
+# N_therm = f_therm * w = 30 w attempts per walker.
+EQ7_COUNTS = {
+    64: dict(zip(range(10, 38), [17, 21, 26, 31, 36, 42, 49, 56, 63, 71, 80, 89, 99, 109, 120, 132,
+                                 144, 156, 170, 183, 198, 213, 229, 245, 262, 280, 298, 317])),
+    40: dict(zip(range(10, 38), [27, 34, 41, 49, 57, 67, 77, 89, 101, 114, 127, 142, 158, 174, 192, 210,
+                                 229, 250, 271, 293, 316, 341, 366, 392, 419, 447, 477, 507])),
+}
+EQ7_GROWTH = {64: [349, 384, 422, 464], 40: [558, 613, 675, 742]}
+
+
+def test_schedule_counts_equal_eq7_worked_by_hand():
+    L = 6
+    for W, seed in ((64, 5), (40, 3)):
+        o = oracle.OracleMuca(L, W, seed)
+        ok, steps = run_paper_schedule(o, max_iterations=60)
+        assert steps[0]["width"] == 10 and steps[0]["update_attempts"] == EQ7_COUNTS[W][10]
+        assert steps[0]["therm_attempts"] == 300
+        first_full = next(i for i, s in enumerate(steps) if s["width"] == L * L + 1)
+        for s in steps[:first_full + 1]:
+            assert s["update_attempts"] == EQ7_COUNTS[W][s["width"]], (W, s)
+            assert s["therm_attempts"] == 30 * s["width"]
+        assert steps[first_full]["update_attempts"] == EQ7_COUNTS[W][37]
+        grown = [s["update_attempts"] for s in steps[first_full + 1:first_full + 5]]
+        assert len(grown) == 4, "the schedule stopped before four growth iterations"
+        assert grown == EQ7_GROWTH[W]
