@@ -126,15 +126,19 @@ typedef struct muca_info {
 } muca_info;
 
 /* Device bytes an instance with these parameters holds (lattices, energies,
- * histogram, threshold table), for admission by memory footprint.
+ * histogram, threshold table), for admission by memory footprint (the
+ * program summary notes that system size and walker count are limited by the
+ * GPU's memory; Sec. 2.3 lays one lattice per walker out in device memory).
  * Returns 0 for invalid parameters.                                         */
 size_t muca_state_bytes(const muca_params* p);
 
-/* Create an instance: allocate (or carve from device_workspace, which must
+/* Create an instance (Sec. 2.2: W independent walkers, each with its own
+ * lattice, sharing one weight table; Sec. 3, Eq. 5: the Ising energy of each
+ * lattice): allocate (or carve from device_workspace, which must
  * hold muca_state_bytes(p) bytes, be 256-byte aligned and stay alive until
  * muca_destroy) and draw the initial random +-1 spins of every walker on the
- * device, with their energies.  omega starts at 0 in every bin and the sweep
- * counter at 0.  hip_stream: a hipStream_t, or NULL for a stream of the
+ * device, with their energies.  omega starts at 0 in every bin (W = 1, the
+ * first iteration of Sec. 2.1) and the sweep counter at 0.  hip_stream: a hipStream_t, or NULL for a stream of the
  * instance's own.  On failure *out is NULL and muca_last_error(NULL) tells
  * why.                                                                      */
 int muca_create(const muca_params* p, void* hip_stream, void* device_workspace,
@@ -204,24 +208,33 @@ typedef struct muca_schedule_step {
 int muca_run_schedule(muca_instance* h, const muca_schedule* schedule, muca_schedule_step* steps,
                       uint32_t max_steps, uint32_t* iterations);
 
-/* Histogram H[k], k = 0..N, of the most recent recorded call.  n_bins must
- * equal N+1.                                                                */
+/* Histogram H[k], k = 0..N, of the most recent recorded call: the sum over
+ * all walkers of their energy histograms (Sec. 2.2, Fig. 1: H = sum_i H_i;
+ * Sec. 2.3: one entry after every attempted flip).  n_bins must equal N+1.  */
 int muca_histogram(const muca_instance* h, uint64_t* out, size_t n_bins);
 
-/* Current log weights omega[k] (n_bins == N+1).                             */
+/* Current log weights omega[k] = ln W(E_k) (Sec. 2.1: the weights that
+ * Eq. 4 updates; n_bins == N+1).                                            */
 int muca_log_weights(const muca_instance* h, double* out, size_t n_bins);
 
-/* Replace omega (n_bins == N+1, every value finite).                        */
+/* Replace omega = ln W (Sec. 2.1, Eq. 4: any positive weight function may
+ * seed the recursion; Sec. 3.1 times the kernel at fixed, exact weights;
+ * n_bins == N+1, every value finite).                                       */
 int muca_set_log_weights(muca_instance* h, const double* in, size_t n_bins);
 
 /* Threshold table T[k*5 + d] (n == 5*(N+1)) used by the most recent sweep
- * call, or computed from the current omega if there was none.               */
+ * call, or computed from the current omega if there was none: the Metropolis
+ * acceptance min(1, W(E')/W(E)) of Sec. 2.3 as an integer bound on the
+ * 32-bit draw (d = dE/4 + 2, dE the energy change of the flip).             */
 int muca_thresholds(const muca_instance* h, uint64_t* out, size_t n);
 
-/* Current energy of every walker (n == walkers).                            */
+/* Current energy of every walker (Sec. 3, Eq. 5: E = -sum over nearest-
+ * neighbour bonds of s_i s_j, J = 1; n == walkers).                         */
 int muca_energies(const muca_instance* h, int32_t* out, size_t walkers);
 
-/* Current spins, walker-major, +1/-1: out[w*N + i] (n == walkers*N).        */
+/* Current spins of every walker's lattice (Sec. 3, Eq. 5: s_i = +1 or -1 on
+ * the periodic L x L lattice), walker-major: out[w*N + i], i = y*L + x
+ * (n == walkers*N).                                                         */
 int muca_spins(const muca_instance* h, int8_t* out, size_t n);
 
 /* ln g[k] estimated from the stored histogram and omega (Sec. 3.3):
