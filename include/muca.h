@@ -126,9 +126,10 @@ typedef struct muca_info {
 } muca_info;
 
 /* Device bytes an instance with these parameters holds (lattices, energies,
- * histogram, threshold table), for admission by memory footprint (the
- * program summary notes that system size and walker count are limited by the
- * GPU's memory; Sec. 2.3 lays one lattice per walker out in device memory).
+ * histogram, threshold table), for admission by memory footprint
+ * ("Restrictions" of the program summary: system size and walker count are
+ * bounded by the GPU's memory; Sec. 2.3 keeps one lattice per walker in
+ * device memory).
  * Returns 0 for invalid parameters.                                         */
 size_t muca_state_bytes(const muca_params* p);
 
