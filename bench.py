@@ -156,20 +156,26 @@ def kernel_source_hash():
 def traffic_per_launch():
     """HBM bytes per sweep launch of the benchmark shape from the committed
     counter summary (FETCH_SIZE and WRITE_SIZE, each scaled by what it reads
-    for a plain copy), or None if the kernel sources changed since the
-    counters were taken.  The lattices stay in L2 during a launch, so the
-    count does not grow with the sweeps per launch."""
+    for a plain copy) and a note of where they came from; the bytes are None
+    if the kernel sources changed since the counters were taken.  The
+    lattices stay in L2 during a launch, so the count does not grow with the
+    sweeps per launch."""
+    rel = os.path.relpath(TRAFFIC_FILE, ROOT)
+    src = kernel_source_hash()
     if not os.path.exists(TRAFFIC_FILE):
-        return None
+        return None, "no counter summary (%s missing)" % rel
     vals = {}
     with open(TRAFFIC_FILE) as f:
         for line in f:
             if "=" in line and not line.startswith("#"):
                 k, v = line.split("=", 1)
                 vals[k.strip()] = v.strip()
-    if vals.get("kernel_source_sha256_16") != kernel_source_hash():
-        return None
-    return float(vals["hbm_bytes_per_launch"])
+    taken = vals.get("kernel_source_sha256_16")
+    if taken != src:
+        return None, ("%s was taken on kernel sources %s, not the current %s: not used" % (rel, taken, src))
+    return float(vals["hbm_bytes_per_launch"]), (
+        "rocprofv3 FETCH_SIZE + WRITE_SIZE from %s (kernel sources %s, the ones built here), "
+        "not measured in this run" % (rel, src))
 
 
 def scaled_log_weights(L):
@@ -375,8 +381,11 @@ def bench_served(args):
     from paper_1707_00919_amd import Server, Solver
     from muca_inputs import SERVE_REQUEST as Q, serving_requests
     reqs = serving_requests(duration=args.serve_duration)
-    srv = Server(64 << 30, max_active_walkers=args.serve_max_walkers, batch_flags=1, policy=args.serve_policy)
+    srv = Server(64 << 30, max_active_walkers=args.serve_max_walkers, batch_flags=1, policy=args.serve_policy,
+                 max_wait_s=args.serve_max_wait)
     t0 = time.perf_counter()
+    # the server's clock (seconds since it was created) on this loop's clock
+    clock_off = (time.perf_counter() - t0) - srv.stats()["clock_s"]
     tickets = {}
     nxt = 0
     results = {}
@@ -423,8 +432,12 @@ def bench_served(args):
         dt = time.perf_counter() - t1
         solo = {"requests": min(args.serve_solo_sample, len(reqs)), "attempts_per_s": att_s / dt,
                 "wall_s": dt, "bit_identical_to_served": same}
-    lat = [r["t_done"] - r["t_submit"] for r in results.values()]
-    ttcw = [r["t_weights"] - r["t_submit"] for r in results.values()]
+    # latency from each request's scheduled arrival, not from the moment the
+    # loop got round to submitting it (progress() can block briefly), so a
+    # late submission does not hide waiting time
+    lat = [r["t_done"] + clock_off - reqs[i][0] for i, r in results.items()]
+    ttcw = [r["t_weights"] + clock_off - reqs[i][0] for i, r in results.items()]
+    submit_lag = [r["t_submit"] + clock_off - reqs[i][0] for i, r in results.items()]
     att = sum(r["attempts"] for r in results.values())
     out = {
         "metric": "served multicanonical solves: aggregate attempts/s; p50/p99 latency",
@@ -435,9 +448,11 @@ def bench_served(args):
                    "arrival_rate_per_s": 20.0, "arrival_window_s": args.serve_duration,
                    "L": [16, 24, 32, 48, 64], "walkers": [1024, 16384],
                    "mem_cap_bytes": 64 << 30, "max_active_walkers": args.serve_max_walkers,
-                   "admission": args.serve_policy,
+                   "admission": args.serve_policy, "max_wait_s": args.serve_max_wait,
                    **Q},
         "latency_p50_s": nearest_rank(lat, 50), "latency_p99_s": nearest_rank(lat, 99),
+        "latency_from": "scheduled arrival",
+        "submit_lag_max_s": max(submit_lag), "submit_lag_p99_s": nearest_rank(submit_lag, 99),
         "ttcw_p50_s": nearest_rank(ttcw, 50), "ttcw_p99_s": nearest_rank(ttcw, 99),
         "converged": sum(1 for r in results.values() if r["status"] == 0),
         "failed": sum(1 for r in results.values() if r["status"] not in (0, 5)),
@@ -606,6 +621,9 @@ def main():
     ap.add_argument("--serve-max-walkers", type=int, default=1 << 19)
     ap.add_argument("--serve-policy", choices=["fifo", "smallest-first"], default="fifo",
                     help="served_poisson20: admission order of queued requests")
+    ap.add_argument("--serve-max-wait", type=float, default=30.0,
+                    help="served_poisson20 with smallest-first: a request queued longer than this "
+                         "goes first")
     ap.add_argument("--serve-solo-sample", type=int, default=24,
                     help="solve this many of the first requests alone, one per launch, "
                          "for the comparison rate")
@@ -663,7 +681,8 @@ def main():
             variant_ms[v] = variant_ms.get(v, 0.0) + ms
     main_variant = max(variant_ms, key=variant_ms.get)
     # the committed counter summary covers the headline shape only
-    traffic = traffic_per_launch() if args.workload == WORKLOAD else None
+    traffic, traffic_source = traffic_per_launch() if args.workload == WORKLOAD else (
+        None, "counters are kept for the headline shape only")
     avg_launch_s = kernel_ms * 1e-3 / launches
     attempts_per_launch = attempts / launches
     achieved = ALU_OPS_PER_ATTEMPT * attempts_per_launch / avg_launch_s
@@ -692,7 +711,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "L": wl["L"], "walkers": wl["walkers"],
                    "iter_sweeps": wl["iter_sweeps"], "min_flatness": wl["min_flat"],
-                   "production_sweeps": wl["prod_sweeps"], "therm_sweeps": wl["therm_sweeps"],
+                   "production_sweeps": wl["prod_sweeps"],
+                   "production_therm_sweeps": wl["prod_therm_sweeps"],
+                   "therm_sweeps": wl["therm_sweeps"],
                    "seeds": "1..%d" % args.steps},
         "ttc_p50_s": nearest_rank(ttc, 50),
         "ttc_p99_s": nearest_rank(ttc, 99),
@@ -700,6 +721,8 @@ def main():
         "iterations_max": max(r["iterations"] for r in runs),
         "converged": sum(r["converged"] for r in runs),
         "ln_g_max_abs_err": max(errs) if errs else None,
+        "ln_g_note": "with production_therm_sweeps unrecorded sweeps at the final weights before the "
+                     "recorded production sweeps; they are counted in value",
         "sweep_kernel_attempts_per_s": attempts / (kernel_ms * 1e-3),
         "roofline": {
             "bound": "alu",
@@ -708,6 +731,7 @@ def main():
             "unit": "Tops/s",
             "frac": achieved / VALU_PEAK_OPS,
             "traffic": traffic,
+            "traffic_source": traffic_source,
             "kernel": KERNEL_NAMES[main_variant] + "<%d>" % wl["L"],
             "kernel_time_share": variant_ms[main_variant] / kernel_ms,
             "avg_launch_ms": avg_launch_s * 1e3,

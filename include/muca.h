@@ -395,7 +395,15 @@ typedef struct muca_server_config {
     uint32_t policy;              /* MUCA_SERVE_FIFO: admit in arrival order;
                                      MUCA_SERVE_SMALLEST_FIRST: admit the
                                      queued request of least estimated work
-                                     (walkers * N^2) first                   */
+                                     first -- walkers * N * (N/20 iterations,
+                                     capped by max_iterations, of iter_therm +
+                                     iter_sweeps sweeps, plus prod_therm +
+                                     prod_sweeps) -- except that a request
+                                     queued for longer than max_wait_s goes
+                                     before any other (the oldest first), so
+                                     that no request waits without bound     */
+    double max_wait_s;            /* smallest-first only; 0 means 30 s; must
+                                     be >= 0                                 */
 } muca_server_config;
 #define MUCA_SERVE_FIFO 0u
 #define MUCA_SERVE_SMALLEST_FIRST 1u

@@ -69,7 +69,8 @@ class ScheduleStep(ctypes.Structure):
 
 class ServerConfig(ctypes.Structure):
     _fields_ = [("mem_cap_bytes", ctypes.c_uint64), ("max_active_walkers", ctypes.c_uint64),
-                ("batch_flags", ctypes.c_uint32), ("policy", ctypes.c_uint32)]
+                ("batch_flags", ctypes.c_uint32), ("policy", ctypes.c_uint32),
+                ("max_wait_s", ctypes.c_double)]
 
 
 class Request(ctypes.Structure):

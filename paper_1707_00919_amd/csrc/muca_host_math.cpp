@@ -218,4 +218,29 @@ std::vector<Segment> segments_of(uint64_t N, uint64_t pos0, uint64_t therm, uint
     return out;
 }
 
+double solve_work_estimate(uint32_t L, uint32_t walkers, uint32_t iter_therm, uint32_t iter_sweeps,
+                           uint32_t max_iterations, uint32_t prod_therm, uint32_t prod_sweeps)
+{
+    const double n = (double)L * L;
+    double iterations = std::max(1.0, n / 20.0);
+    if (max_iterations)
+        iterations = std::min(iterations, (double)max_iterations);
+    const double sweeps = iterations * ((double)iter_therm + iter_sweeps) + prod_therm + prod_sweeps;
+    return (double)walkers * n * sweeps;
+}
+
+size_t admission_pick(const QueuedJob* q, size_t n, bool smallest_first, double now, double max_wait_s)
+{
+    if (n == 0 || !smallest_first)
+        return 0;
+    for (size_t i = 0; i < n; ++i)  // arrival order: the first overdue one is the oldest
+        if (now - q[i].t_submit > max_wait_s)
+            return i;
+    size_t best = 0;
+    for (size_t i = 1; i < n; ++i)
+        if (q[i].work < q[best].work)
+            best = i;
+    return best;
+}
+
 }  // namespace muca_host

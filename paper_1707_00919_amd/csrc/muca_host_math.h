@@ -47,6 +47,27 @@ struct Segment {
 // sweeps for the range kernel.
 std::vector<Segment> segments_of(uint64_t N, uint64_t pos0, uint64_t therm, uint64_t recorded);
 
+// Estimated attempts of one served solve: walkers * N per sweep, times the
+// sweeps it asks for -- its weight iterations of iter_therm + iter_sweeps
+// sweeps each, then prod_therm + prod_sweeps.  The number of iterations to a
+// flat histogram is taken to grow like N (about N / 20: 48 at L = 32 with
+// 16384 walkers and 200-sweep iterations), capped by max_iterations when that
+// is set.
+double solve_work_estimate(uint32_t L, uint32_t walkers, uint32_t iter_therm, uint32_t iter_sweeps,
+                           uint32_t max_iterations, uint32_t prod_therm, uint32_t prod_sweeps);
+
+// The serving queue's admission order.  Entries are in arrival order.  FIFO
+// (smallest_first false) takes entry 0.  Smallest-first takes the entry of
+// least work (ties: the earlier arrival) -- unless some entry has waited
+// longer than max_wait_s at time now, in which case the oldest such entry
+// goes first, so that no request waits without bound behind a stream of
+// smaller ones.
+struct QueuedJob {
+    double work;
+    double t_submit;
+};
+size_t admission_pick(const QueuedJob* q, size_t n, bool smallest_first, double now, double max_wait_s);
+
 constexpr size_t kArenaAlign = 256;
 
 // First-fit allocator over [0, size) with coalescing of free neighbours: the

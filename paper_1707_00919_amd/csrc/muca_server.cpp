@@ -8,7 +8,8 @@
 // until it is done, and runs the admitted requests together:
 //
 //   queue    requests wait in arrival order (or, with the smallest-first
-//            policy, the one of least estimated work goes next); the next one
+//            policy, the one of least estimated work goes next, unless one
+//            has waited longer than the configured bound); the next one
 //            is admitted when its device state (muca_state_bytes) fits in the
 //            free part of the server's arena and the walker budget allows it;
 //   lanes    admitted requests are grouped by L; each lane is one batch
@@ -67,6 +68,7 @@ struct Request {
     std::string err;
     uint64_t attempts = 0;
     double t_submit = 0, t_admit = -1, t_weights = -1, t_done = -1;
+    double work = 0;  // estimated attempts (muca_host::solve_work_estimate)
 };
 
 struct Lane {
@@ -169,28 +171,24 @@ void retire(muca_server* s, Request* r, int status, const std::string& why)
     ++s->completed;
 }
 
-// Estimated work of a solve: walkers * N attempts per sweep, times the
-// iterations to a flat histogram, which grow about like N.
-double work_of(const Request* r)
-{
-    const double n = (double)r->q.L * r->q.L;
-    return (double)r->q.walkers * n * n;
-}
-
 // Admits queued requests while the next one fits: in arrival order, or with
 // MUCA_SERVE_SMALLEST_FIRST the one of least estimated work first (ties in
-// arrival order).
+// arrival order) unless a request has waited longer than max_wait_s
+// (muca_host::admission_pick).  The picked request is moved to the front and
+// blocks the queue until it fits.
 int admit(muca_server* s)
 {
+    std::vector<muca_host::QueuedJob> jobs;
     while (!s->queue.empty()) {
         if (s->cfg.policy == MUCA_SERVE_SMALLEST_FIRST) {
-            auto best = s->queue.begin();
-            for (auto it = s->queue.begin(); it != s->queue.end(); ++it)
-                if (work_of(*it) < work_of(*best))
-                    best = it;
-            if (best != s->queue.begin()) {
-                Request* b = *best;
-                s->queue.erase(best);
+            jobs.clear();
+            for (const Request* r : s->queue)
+                jobs.push_back({r->work, r->t_submit});
+            const double wait = s->cfg.max_wait_s > 0.0 ? s->cfg.max_wait_s : 30.0;
+            const size_t i = muca_host::admission_pick(jobs.data(), jobs.size(), true, now_s(s), wait);
+            if (i != 0) {
+                Request* b = s->queue[i];
+                s->queue.erase(s->queue.begin() + (std::ptrdiff_t)i);
                 s->queue.push_front(b);
             }
         }
@@ -365,6 +363,8 @@ int muca_server_create(const muca_server_config* cfg, muca_server** out)
         return sfail(nullptr, MUCA_ERR_INVALID_ARG, "unknown batch flag");
     if (cfg->policy > MUCA_SERVE_SMALLEST_FIRST)
         return sfail(nullptr, MUCA_ERR_INVALID_ARG, "unknown admission policy");
+    if (!(cfg->max_wait_s >= 0.0))
+        return sfail(nullptr, MUCA_ERR_INVALID_ARG, "max_wait_s must be >= 0");
     muca_server* s = new (std::nothrow) muca_server();
     if (!s)
         return sfail(nullptr, MUCA_ERR_OUT_OF_MEMORY, "host allocation failed");
@@ -397,6 +397,8 @@ static int muca_server_submit_impl(muca_server* s, const muca_request* q, uint64
     r->ticket = s->next_ticket++;
     r->q = *q;
     r->t_submit = now_s(s);
+    r->work = muca_host::solve_work_estimate(q->L, q->walkers, q->iter_therm, q->iter_sweeps, q->max_iterations,
+                                             q->prod_therm, q->prod_sweeps);
     Request* raw = r.get();
     s->requests[raw->ticket] = std::move(r);
     try {

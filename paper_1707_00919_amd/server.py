@@ -15,15 +15,18 @@ from .solver import MucaError
 
 
 class Server:
-    def __init__(self, mem_cap_bytes, max_active_walkers=0, batch_flags=0, policy="fifo"):
+    def __init__(self, mem_cap_bytes, max_active_walkers=0, batch_flags=0, policy="fifo", max_wait_s=0.0):
         """policy: "fifo" admits in arrival order; "smallest-first" admits the
-        queued request of least estimated work (walkers * N^2) first."""
+        queued request of least estimated work (walkers * N * its sweeps, with
+        about N/20 weight iterations) first, except that a request queued for
+        longer than max_wait_s (0: 30 s) goes before any other."""
         policies = {"fifo": _abi.MUCA_SERVE_FIFO, "smallest-first": _abi.MUCA_SERVE_SMALLEST_FIRST}
         if policy not in policies:
             raise ValueError("policy must be 'fifo' or 'smallest-first'")
         self._lib = _abi.lib()
         self._s = ctypes.c_void_p()
-        cfg = _abi.ServerConfig(int(mem_cap_bytes), int(max_active_walkers), int(batch_flags), policies[policy])
+        cfg = _abi.ServerConfig(int(mem_cap_bytes), int(max_active_walkers), int(batch_flags), policies[policy],
+                                float(max_wait_s))
         rc = self._lib.muca_server_create(ctypes.byref(cfg), ctypes.byref(self._s))
         if rc != _abi.MUCA_OK:
             msg = self._lib.muca_server_last_error(None)

@@ -281,6 +281,24 @@ def test_full_size_L32_two_weight_iterations():
     assert_state(s, o)
 
 
+def test_headline_seed1_first_three_weight_iterations():
+    # the paper-scale workload exactly as the benchmark runs it: L = 32, 16384
+    # walkers, seed 1, omega = 0 at the start, 200-sweep weight iterations
+    # (Sec. 3.1 scale; Eq. 4 after each); histogram, threshold table, omega
+    # bits, spins and energies of every walker equal the oracle's after each
+    # of the first three iterations
+    from muca_inputs import WORKLOADS
+    wl = WORKLOADS["ising_L32_W16384"]
+    L, W = wl["L"], wl["walkers"]
+    s = Solver(L, W, 1)
+    o = oracle.OracleMuca(L, W, 1)
+    for it in range(3):
+        note("headline L=32 W=16384 seed 1, iteration %d of 200 sweeps" % (it + 1))
+        assert_call(s.iterate(wl["therm_sweeps"], wl["iter_sweeps"]),
+                    o.iterate(wl["therm_sweeps"], wl["iter_sweeps"]), s, o)
+        assert_state(s, o)
+
+
 def test_invalid_arguments_are_reported():
     from paper_1707_00919_amd import MucaError, _abi
     note("error paths")
