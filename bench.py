@@ -591,6 +591,29 @@ def bench_production(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_issue_probe(args):
+    """Issue rates of the integer vector instructions the sweep is made of
+    (muca_probe_issue_rate): lane-operations per second of each, with one and
+    with eight waves per SIMD, against the ALU peak the roofline uses."""
+    import ctypes
+    from paper_1707_00919_amd import _abi
+    lib = _abi.lib()
+    rows = []
+    for name, op in _abi.MUCA_PROBE_OPS.items():
+        for wps in (1, 2, 8):
+            ms, ops = ctypes.c_double(), ctypes.c_uint64()
+            rc = lib.muca_probe_issue_rate(op, wps, args.probe_iterations, ctypes.byref(ms), ctypes.byref(ops))
+            if rc != 0:
+                raise RuntimeError("muca_probe_issue_rate failed: %d" % rc)
+            rate = ops.value / (ms.value * 1e-3)
+            rows.append({"instruction": name, "waves_per_simd": wps, "ms": ms.value, "lane_ops": ops.value,
+                         "lane_ops_per_s": rate, "frac_of_peak": rate / VALU_PEAK_OPS})
+            print("%-22s %d waves/SIMD: %.3e lane-ops/s (%.3f of %.3e)" %
+                  (name, wps, rate, rate / VALU_PEAK_OPS, VALU_PEAK_OPS), file=sys.stderr, flush=True)
+    print(json.dumps({"issue_probe": rows, "peak_lane_ops_per_s": VALU_PEAK_OPS,
+                      "iterations": args.probe_iterations}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -627,6 +650,9 @@ def main():
     ap.add_argument("--serve-solo-sample", type=int, default=24,
                     help="solve this many of the first requests alone, one per launch, "
                          "for the comparison rate")
+    ap.add_argument("--issue-probe", action="store_true",
+                    help="measure the issue rate of the sweep's integer instructions (the ALU roof)")
+    ap.add_argument("--probe-iterations", type=int, default=16384)
     ap.add_argument("--profile-pass", action="store_true",
                     help="short sweep + calibration copy for rocprofv3 counter runs")
     args = ap.parse_args()
@@ -642,6 +668,8 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
     torch.cuda.set_device(0)
+    if args.issue_probe:
+        return bench_issue_probe(args)
     if args.workload == "batched48":
         return bench_batched(args)
     if args.workload == "served_poisson20":

@@ -464,6 +464,24 @@ int muca_server_destroy(muca_server* s);
 
 const char* muca_server_last_error(const muca_server* s);
 
+/* ------------------------------------------------------------------------
+ * Measurement: the issue rate of the integer vector instructions the sweep is
+ * made of (Philox4x32-10 and the Metropolis step, Sec. 2.3), which sets the
+ * roof the sweep kernels are measured against (Sec. 3.1 times the hardware
+ * performance per attempted flip).  Every lane of waves_per_simd (1..8)
+ * waves on each SIMD of every compute unit advances eight independent chains
+ * of instruction `op` for 64 * iterations steps (iterations <= 2^24).  *ms is
+ * the kernel's device time, *lane_ops the lane-operations of the probed
+ * instruction it executed; lane_ops / ms is the measured rate.  Allocates a
+ * small output buffer and a stream of its own.                             */
+#define MUCA_PROBE_ADD 0u     /* v_add_u32                                  */
+#define MUCA_PROBE_XOR3 1u    /* v_bitop3_b32 as a three-input xor          */
+#define MUCA_PROBE_MUL_LO 2u  /* v_mul_lo_u32                               */
+#define MUCA_PROBE_MUL_HI 3u  /* v_mul_hi_u32                               */
+#define MUCA_PROBE_MAD_U64 4u /* v_mad_u64_u32                              */
+int muca_probe_issue_rate(uint32_t op, uint32_t waves_per_simd, uint32_t iterations, double* ms,
+                          uint64_t* lane_ops);
+
 #ifdef __cplusplus
 }
 #endif

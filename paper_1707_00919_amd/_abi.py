@@ -144,6 +144,8 @@ PROTOTYPES = {
     "muca_server_stats": (_INT, [_P, ctypes.POINTER(ServerCounters)]),
     "muca_server_destroy": (_INT, [_P]),
     "muca_server_last_error": (ctypes.c_char_p, [_P]),
+    "muca_probe_issue_rate": (_INT, [_U32, _U32, _U32, ctypes.POINTER(ctypes.c_double),
+                                     ctypes.POINTER(ctypes.c_uint64)]),
 }
 
 MUCA_BATCH_SKIP = 0
@@ -153,6 +155,8 @@ MUCA_SERVE_FIFO = 0
 MUCA_SERVE_SMALLEST_FIRST = 1
 MUCA_STOP_KL = 0
 MUCA_STOP_CHEBYSHEV = 1
+MUCA_PROBE_OPS = {"v_add_u32": 0, "v_bitop3_b32 (xor3)": 1, "v_mul_lo_u32": 2, "v_mul_hi_u32": 3,
+                  "v_mad_u64_u32": 4}
 MUCA_BATCH_GRAPH = 0x1
 MUCA_BATCH_AUTOTUNE = 0x2
 
