@@ -260,8 +260,8 @@ size_t muca_checkpoint_bytes(const muca_instance* h);
 int muca_checkpoint(const muca_instance* h, void* out, size_t n);
 int muca_restore(muca_instance* h, const void* in, size_t n);
 
-/* Message for the last failure on h (NULL: the last failed muca_create of
- * this thread).  Valid until the next call on h.                            */
+/* Message for the last failure on h (NULL: the last failed muca_create or
+ * muca_production_static of this thread).  Valid until the next call on h.  */
 const char* muca_last_error(const muca_instance* h);
 
 /* ------------------------------------------------------------------------
@@ -463,6 +463,40 @@ int muca_server_stats(const muca_server* s, muca_server_counters* out);
 int muca_server_destroy(muca_server* s);
 
 const char* muca_server_last_error(const muca_server* s);
+
+/* ------------------------------------------------------------------------
+ * Production sweeps that allocate nothing -- for callers that cannot
+ * allocate device or host memory while they run (serving loops and harnesses
+ * that forbid allocation).  Same operation and bits as muca_production on an
+ * instance in the same state, on lattices and energies the caller owns.
+ *
+ * p: L, walkers, seed and flags as in muca_create.  sweep0: the sweep index
+ * of the first sweep (an instance's muca_info.sweep_counter); the call runs
+ * sweeps sweep0 .. sweep0 + therm_sweeps + sweeps - 1 of every walker, the
+ * last `sweeps` recorded.  omega: host, N+1 finite log weights (not changed).
+ * spins, energies: device memory in an instance's layout, read and written --
+ * spins uint32 [L * ceil(L/32)][wpad], bit x%32 of word y*ceil(L/32) + x/32 of
+ * walker w at index word*wpad + w (bit set = +1), energies int32 [wpad], with
+ * wpad = walkers rounded up to a multiple of 64 (the padding walkers run but
+ * are never counted).  hist: host, N+1 counts, written.  hip_stream: a
+ * hipStream_t, or NULL for the null stream; the call returns after its work
+ * there is done.
+ *
+ * The uploaded thresholds and the merged histogram live in one static
+ * device array of MUCA_STATIC_SCRATCH_BYTES per device (enough for L =
+ * MUCA_MAX_L), held until the process ends; the histogram part is cleared by
+ * a kernel at the start of every call.  All calls on a device share that
+ * array, so calls whose device work overlapped would race: the library holds
+ * a process-wide lock for the whole call, and calls from several threads run
+ * one after the other.  No hipMalloc, hipFree or host heap allocation is
+ * made.  Errors: MUCA_ERR_INVALID_ARG (NULL pointer, invalid parameters,
+ * non-finite omega, tables beyond the scratch size), MUCA_ERR_OVERFLOW,
+ * MUCA_ERR_DEVICE (a HIP call failed or the histogram sum is wrong);
+ * muca_last_error(NULL) tells why.                                          */
+#define MUCA_STATIC_SCRATCH_BYTES 655872u
+int muca_production_static(const muca_params* p, uint64_t sweep0, uint32_t therm_sweeps, uint32_t sweeps,
+                           const double* omega, uint32_t* spins, int32_t* energies, uint64_t* hist,
+                           void* hip_stream);
 
 /* ------------------------------------------------------------------------
  * Measurement: the issue rate of the integer vector instructions the sweep is

@@ -146,7 +146,10 @@ PROTOTYPES = {
     "muca_server_last_error": (ctypes.c_char_p, [_P]),
     "muca_probe_issue_rate": (_INT, [_U32, _U32, _U32, ctypes.POINTER(ctypes.c_double),
                                      ctypes.POINTER(ctypes.c_uint64)]),
+    "muca_production_static": (_INT, [ctypes.POINTER(MucaParams), ctypes.c_uint64, _U32, _U32, _P, _P, _P, _P,
+                                      _P]),
 }
+MUCA_STATIC_SCRATCH_BYTES = 655872
 
 MUCA_BATCH_SKIP = 0
 MUCA_BATCH_ITERATE = 1

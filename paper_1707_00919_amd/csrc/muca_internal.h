@@ -58,6 +58,31 @@ struct muca_instance {
 
 namespace muca_host {
 
+// Device buffers and shape of one sweep call (an instance's, or those the
+// caller of the allocation-free production call hands in).
+struct CallTarget {
+    uint32_t L, wpad, walkers, seed, flags;
+    int cus;
+    uint32_t* d_spins;
+    int32_t* d_energy;
+    unsigned long long* d_hist;  // N + 1 bins
+    uint64_t* d_table;           // 32 (N + 1) bytes
+    uint64_t* h_table4;          // host staging of the device table, same size
+};
+
+// Picks the kernel form for the thresholds table5 (T[k*5 + d]), writes the
+// device form of the table into t.h_table4 and enqueues on `stream`: its
+// upload, the histogram clear and the launches of every segment (between
+// ev_start and ev_stop when they are not null).  Nothing is waited for.
+// Returns the first failing HIP call's error, *what naming it.
+hipError_t enqueue_call(const CallTarget& t, const uint64_t* table5, const Segment* segs, size_t nsegs,
+                        hipStream_t stream, hipEvent_t ev_start, hipEvent_t ev_stop, uint32_t* launches,
+                        uint32_t* variant, const char** what);
+
+// Sets the message muca_last_error(NULL) returns on this thread (copied into
+// a fixed buffer; never allocates).
+void set_null_error(const char* msg);
+
 // Apply the results of a finished recorded call (histogram already in
 // h->hist): checks sum H, fills the statistics, applies Eq. 4 when `update`.
 // Returns MUCA_OK or an error code (the instance is then poisoned).

@@ -74,9 +74,21 @@ muca_host::Layout layout_for(const muca_params* p)
     return l;
 }
 
-thread_local std::string g_create_error;
+// Message of the last failure with no instance to hold it (muca_create, the
+// allocation-free production call): a fixed buffer, so that setting it never
+// allocates.
+thread_local char g_null_error[256];
 
 }  // namespace
+
+namespace muca_host {
+
+void set_null_error(const char* msg)
+{
+    std::snprintf(g_null_error, sizeof g_null_error, "%s", msg);
+}
+
+}  // namespace muca_host
 
 namespace {
 
@@ -85,7 +97,7 @@ int fail(muca_instance* h, int code, const std::string& msg)
     if (h)
         h->err = msg;
     else
-        g_create_error = msg;
+        muca_host::set_null_error(msg.c_str());
     return code;
 }
 
@@ -195,6 +207,133 @@ void release(muca_instance* h)
     delete h;
 }
 
+}  // namespace
+
+namespace muca_host {
+
+hipError_t enqueue_call(const CallTarget& t, const uint64_t* table5, const Segment* segs, size_t nsegs,
+                        hipStream_t stream, hipEvent_t ev_start, hipEvent_t ev_stop, uint32_t* launches_out,
+                        uint32_t* variant_out, const char** what)
+{
+    const uint32_t N = t.L * t.L;
+    const size_t table_bytes = (size_t)(N + 1) * 4 * sizeof(uint64_t);
+    // kernel choice: 4 wide two-wave, 3 wide, 2 split, 1 fast, 0 generic (all
+    // give the same bits)
+    uint32_t variant = 0;
+    if (!(t.flags & MUCA_FLAG_GENERIC_KERNEL) && muca::wide_sweep_supported(t.L) &&
+        fast_table(N, table5, reinterpret_cast<uint32_t*>(t.h_table4), 8)) {
+        // as for L <= 64: a second wave for the random numbers pays while every
+        // workgroup is resident at once
+        const bool two = !(t.flags & MUCA_FLAG_FAST_KERNEL) && muca::wide_split_supported(t.L) &&
+                         muca::prefer_wide_split(t.L, t.wpad / muca::kWave, (uint32_t)t.cus);
+        variant = two ? 4 : 3;
+    } else if (!(t.flags & MUCA_FLAG_GENERIC_KERNEL) &&
+               (muca::split_sweep_supported(t.L) || muca::fast_sweep_supported(t.L)) &&
+               fast_table(N, table5, reinterpret_cast<uint32_t*>(t.h_table4), 5)) {
+        // The split kernel gives each 64 walkers a second wave for the random
+        // numbers; once its workgroups no longer all fit at once, or more than
+        // two share a CU, the one-wave form wins.
+        const bool want_fast = (t.flags & MUCA_FLAG_FAST_KERNEL) != 0 ||
+                               (!muca::prefer_split(t.L, t.wpad / muca::kWave, (uint32_t)t.cus) &&
+                                muca::fast_sweep_supported(t.L));
+        if (muca::split_sweep_supported(t.L) && !(want_fast && muca::fast_sweep_supported(t.L)))
+            variant = 2;
+        else
+            variant = 1;
+    }
+    const bool fast = variant != 0;
+    if (!fast)
+        device_table(N, table5, t.h_table4);
+    *variant_out = variant;
+    *launches_out = 0;
+#define MUCA_ENQ(call, msg)          \
+    do {                             \
+        hipError_t e_ = (call);      \
+        if (e_ != hipSuccess) {      \
+            *what = (msg);           \
+            return e_;               \
+        }                            \
+    } while (0)
+    MUCA_ENQ(hipMemcpyAsync(t.d_table, t.h_table4, table_bytes, hipMemcpyHostToDevice, stream),
+             "threshold upload");
+    MUCA_ENQ(muca::launch_fill_u64(t.d_hist, N + 1, stream), "histogram clear");
+
+    uint32_t chunk = muca::max_sweeps_per_launch(t.L);
+    const uint32_t cap = t.flags & MUCA_FLAG_SWEEPS_PER_LAUNCH_MASK;
+    if (cap != 0 && cap < chunk)
+        chunk = cap;
+    uint32_t launches = 0;
+    if (ev_start)
+        MUCA_ENQ(hipEventRecord(ev_start, stream), "hipEventRecord");
+    for (size_t i = 0; i < nsegs; ++i) {
+        const Segment& g = segs[i];
+        if (g.n == 0) {
+            muca::RangeArgs a{};
+            a.spins = t.d_spins;
+            a.energy = t.d_energy;
+            a.table = t.d_table;
+            a.hist = t.d_hist;
+            a.sweep = g.sweep0;
+            a.L = t.L;
+            a.wpad = t.wpad;
+            a.walkers = t.walkers;
+            a.seed = t.seed;
+            a.site_begin = g.site_begin;
+            a.site_end = g.site_end;
+            a.rec_begin = g.rec_begin;
+            a.table_stride = variant >= 3 ? 8u : (fast ? 5u : 0u);
+            MUCA_ENQ(muca::launch_sweep_range(a, stream), "partial sweep launch");
+            ++launches;
+            continue;
+        }
+        for (uint64_t s0 = 0; s0 < g.n; s0 += chunk) {
+            const uint32_t n = (uint32_t)std::min<uint64_t>(g.n - s0, chunk);
+            const uint32_t th = s0 >= g.therm ? 0u : (uint32_t)std::min<uint64_t>(g.therm - s0, n);
+            if (fast) {
+                muca::FastSweepArgs a{};
+                a.spins = t.d_spins;
+                a.energy = t.d_energy;
+                a.table = reinterpret_cast<const uint32_t*>(t.d_table);
+                a.hist = t.d_hist;
+                a.sweep0 = g.sweep0 + s0;
+                a.wpad = t.wpad;
+                a.walkers = t.walkers;
+                a.seed = t.seed;
+                a.nsweeps = n;
+                a.therm = th;
+                MUCA_ENQ(variant == 4   ? muca::launch_wide_split_sweep(t.L, a, stream)
+                         : variant == 3 ? muca::launch_wide_sweep(t.L, a, stream)
+                         : variant == 2 ? muca::launch_split_sweep(t.L, a, stream)
+                                        : muca::launch_fast_sweep(t.L, a, stream),
+                         "sweep launch");
+            } else {
+                muca::SweepArgs a{};
+                a.spins = t.d_spins;
+                a.energy = t.d_energy;
+                a.table = t.d_table;
+                a.hist = t.d_hist;
+                a.sweep0 = g.sweep0 + s0;
+                a.wpad = t.wpad;
+                a.walkers = t.walkers;
+                a.seed = t.seed;
+                a.nsweeps = n;
+                a.therm = th;
+                MUCA_ENQ(muca::launch_sweep(t.L, a, stream), "sweep launch");
+            }
+            ++launches;
+        }
+    }
+    if (ev_stop)
+        MUCA_ENQ(hipEventRecord(ev_stop, stream), "hipEventRecord");
+#undef MUCA_ENQ
+    *launches_out = launches;
+    return hipSuccess;
+}
+
+}  // namespace muca_host
+
+namespace {
+
 // therm unrecorded, then `recorded` recorded attempts per walker, starting at
 // the instance's position; H -> h->hist.
 int run_attempts(muca_instance* h, uint64_t therm, uint64_t recorded, bool update, muca_info* info)
@@ -219,104 +358,25 @@ int run_attempts(muca_instance* h, uint64_t therm, uint64_t recorded, bool updat
         return fail(h, MUCA_ERR_OUT_OF_MEMORY, "host allocation failed");
     }
     compute_thresholds(N, h->omega.data(), h->table5.data());
-    // kernel choice: 4 wide two-wave, 3 wide, 2 split, 1 fast, 0 generic (all
-    // give the same bits)
-    uint32_t variant = 0;
-    if (!(h->p.flags & MUCA_FLAG_GENERIC_KERNEL) && muca::wide_sweep_supported(h->L) &&
-        fast_table(N, h->table5.data(), reinterpret_cast<uint32_t*>(h->h_table4), 8)) {
-        // as for L <= 64: a second wave for the random numbers pays while every
-        // workgroup is resident at once
-        const bool two = !(h->p.flags & MUCA_FLAG_FAST_KERNEL) && muca::wide_split_supported(h->L) &&
-                         muca::prefer_wide_split(h->L, h->wpad / muca::kWave, (uint32_t)h->cus);
-        variant = two ? 4 : 3;
-    } else if (!(h->p.flags & MUCA_FLAG_GENERIC_KERNEL) &&
-        (muca::split_sweep_supported(h->L) || muca::fast_sweep_supported(h->L)) &&
-        fast_table(N, h->table5.data(), reinterpret_cast<uint32_t*>(h->h_table4), 5)) {
-        // The split kernel gives each 64 walkers a second wave for the random
-        // numbers; once its workgroups no longer all fit at once, or more than
-        // two share a CU, the one-wave form wins.
-        const bool want_fast = (h->p.flags & MUCA_FLAG_FAST_KERNEL) != 0 ||
-                               (!muca::prefer_split(h->L, h->wpad / muca::kWave, (uint32_t)h->cus) &&
-                                muca::fast_sweep_supported(h->L));
-        if (muca::split_sweep_supported(h->L) && !(want_fast && muca::fast_sweep_supported(h->L)))
-            variant = 2;
-        else
-            variant = 1;
-    }
-    const bool fast = variant != 0;
-    if (!fast)
-        device_table(N, h->table5.data(), h->h_table4);
+    muca_host::CallTarget t{};
+    t.L = h->L;
+    t.wpad = h->wpad;
+    t.walkers = h->p.walkers;
+    t.seed = h->p.seed;
+    t.flags = h->p.flags;
+    t.cus = h->cus;
+    t.d_spins = h->d_spins;
+    t.d_energy = h->d_energy;
+    t.d_hist = h->d_hist;
+    t.d_table = h->d_table;
+    t.h_table4 = h->h_table4;
     MUCA_HIP(h, hipSetDevice(h->device), "hipSetDevice");
-    MUCA_HIP(h, hipMemcpyAsync(h->d_table, h->h_table4, h->lay.table_bytes, hipMemcpyHostToDevice,
-                               h->stream),
-             "threshold upload");
-    MUCA_HIP(h, muca::launch_fill_u64(h->d_hist, N + 1, h->stream), "histogram clear");
-
-    uint32_t chunk = muca::max_sweeps_per_launch(h->L);
-    const uint32_t cap = h->p.flags & MUCA_FLAG_SWEEPS_PER_LAUNCH_MASK;
-    if (cap != 0 && cap < chunk)
-        chunk = cap;
-    uint32_t launches = 0;
-    MUCA_HIP(h, hipEventRecord(h->ev_start, h->stream), "hipEventRecord");
-    for (const muca_host::Segment& g : segments) {
-        if (g.n == 0) {
-            muca::RangeArgs a{};
-            a.spins = h->d_spins;
-            a.energy = h->d_energy;
-            a.table = h->d_table;
-            a.hist = h->d_hist;
-            a.sweep = g.sweep0;
-            a.L = h->L;
-            a.wpad = h->wpad;
-            a.walkers = h->p.walkers;
-            a.seed = h->p.seed;
-            a.site_begin = g.site_begin;
-            a.site_end = g.site_end;
-            a.rec_begin = g.rec_begin;
-            a.table_stride = variant >= 3 ? 8u : (fast ? 5u : 0u);
-            MUCA_HIP(h, muca::launch_sweep_range(a, h->stream), "partial sweep launch");
-            ++launches;
-            continue;
-        }
-        for (uint64_t s0 = 0; s0 < g.n; s0 += chunk) {
-            const uint32_t n = (uint32_t)std::min<uint64_t>(g.n - s0, chunk);
-            const uint32_t th = s0 >= g.therm ? 0u : (uint32_t)std::min<uint64_t>(g.therm - s0, n);
-            if (fast) {
-                muca::FastSweepArgs a{};
-                a.spins = h->d_spins;
-                a.energy = h->d_energy;
-                a.table = reinterpret_cast<const uint32_t*>(h->d_table);
-                a.hist = h->d_hist;
-                a.sweep0 = g.sweep0 + s0;
-                a.wpad = h->wpad;
-                a.walkers = h->p.walkers;
-                a.seed = h->p.seed;
-                a.nsweeps = n;
-                a.therm = th;
-                MUCA_HIP(h,
-                         variant == 4   ? muca::launch_wide_split_sweep(h->L, a, h->stream)
-                         : variant == 3 ? muca::launch_wide_sweep(h->L, a, h->stream)
-                         : variant == 2 ? muca::launch_split_sweep(h->L, a, h->stream)
-                                        : muca::launch_fast_sweep(h->L, a, h->stream),
-                         "sweep launch");
-            } else {
-                muca::SweepArgs a{};
-                a.spins = h->d_spins;
-                a.energy = h->d_energy;
-                a.table = h->d_table;
-                a.hist = h->d_hist;
-                a.sweep0 = g.sweep0 + s0;
-                a.wpad = h->wpad;
-                a.walkers = h->p.walkers;
-                a.seed = h->p.seed;
-                a.nsweeps = n;
-                a.therm = th;
-                MUCA_HIP(h, muca::launch_sweep(h->L, a, h->stream), "sweep launch");
-            }
-            ++launches;
-        }
-    }
-    MUCA_HIP(h, hipEventRecord(h->ev_stop, h->stream), "hipEventRecord");
+    uint32_t launches = 0, variant = 0;
+    const char* what = "";
+    hipError_t e = muca_host::enqueue_call(t, h->table5.data(), segments.data(), segments.size(), h->stream,
+                                           h->ev_start, h->ev_stop, &launches, &variant, &what);
+    if (e != hipSuccess)
+        return device_fail(h, e, what);
     MUCA_HIP(h, hipMemcpyAsync(h->h_hist, h->d_hist, h->lay.hist_bytes, hipMemcpyDeviceToHost,
                                h->stream),
              "histogram download");
@@ -369,7 +429,7 @@ int muca_create(const muca_params* p, void* hip_stream, void* device_workspace,
     }
 
     auto bail = [&](int code) {
-        g_create_error = h->err;
+        muca_host::set_null_error(h->err.c_str());
         release(h);
         return code;
     };
@@ -772,7 +832,7 @@ int muca_last_info(const muca_instance* h, muca_info* out)
 
 const char* muca_last_error(const muca_instance* h)
 {
-    return h ? h->err.c_str() : g_create_error.c_str();
+    return h ? h->err.c_str() : g_null_error;
 }
 
 }  // extern "C"

@@ -183,6 +183,31 @@ class Solver:
         return info.as_dict()
 
 
+def production_static(L, walkers, seed, sweep0, therm_sweeps, sweeps, omega, spins, energies, flags=0):
+    """muca_production_static: production sweeps on caller-owned device
+    lattices and energies (torch tensors in an instance's layout, see
+    include/muca.h) on torch's current stream; the library allocates nothing.
+    Returns the histogram (N + 1 counts)."""
+    import torch
+    lib = _abi.lib()
+    L, walkers = int(L), int(walkers)
+    p = _abi.MucaParams(L, walkers, int(seed) & 0xFFFFFFFF, flags)
+    om = np.ascontiguousarray(omega, dtype=np.float64)
+    if om.size != L * L + 1:
+        raise ValueError("omega must hold L*L+1 values")
+    if not (spins.is_cuda and energies.is_cuda and spins.is_contiguous() and energies.is_contiguous()):
+        raise ValueError("spins and energies must be contiguous device tensors")
+    hist = np.zeros(L * L + 1, dtype=np.uint64)
+    stream = ctypes.c_void_p(torch.cuda.current_stream(spins.device).cuda_stream)
+    rc = lib.muca_production_static(ctypes.byref(p), int(sweep0), int(therm_sweeps), int(sweeps), _ptr(om),
+                                    ctypes.c_void_p(spins.data_ptr()), ctypes.c_void_p(energies.data_ptr()),
+                                    _ptr(hist), stream)
+    if rc != _abi.MUCA_OK:
+        msg = lib.muca_last_error(None)
+        raise MucaError(rc, msg.decode() if msg else "")
+    return hist
+
+
 class Batch:
     """Many independent Solvers swept together (the batched form): one round
     runs a weight iteration, a production call or nothing for every member,

@@ -58,6 +58,34 @@ def test_create_rejects_invalid_params_without_a_device(lib):
     assert lib.muca_create(None, None, None, 0, ctypes.byref(h)) == _abi.MUCA_ERR_INVALID_ARG
 
 
+def test_static_production_rejects_invalid_arguments_without_a_device(lib):
+    # argument errors return before any device call (no GPU here)
+    import numpy as np
+    hist = np.zeros(17, dtype=np.uint64)
+    om = np.zeros(17)
+    dummy = ctypes.c_void_p(0x1000)
+    hp = ctypes.c_void_p(hist.ctypes.data)
+    op = ctypes.c_void_p(om.ctypes.data)
+    good = _abi.MucaParams(4, 64, 1, 0)
+    f = lib.muca_production_static
+    assert f(None, 0, 0, 1, op, dummy, dummy, hp, None) == _abi.MUCA_ERR_INVALID_ARG
+    assert f(ctypes.byref(good), 0, 0, 1, None, dummy, dummy, hp, None) == _abi.MUCA_ERR_INVALID_ARG
+    assert f(ctypes.byref(good), 0, 0, 1, op, None, dummy, hp, None) == _abi.MUCA_ERR_INVALID_ARG
+    assert f(ctypes.byref(good), 0, 0, 1, op, dummy, dummy, None, None) == _abi.MUCA_ERR_INVALID_ARG
+    for L, W in [(5, 64), (2, 64), (130, 64), (66, 64), (4, 0)]:
+        p = _abi.MucaParams(L, W, 1, 0)
+        assert f(ctypes.byref(p), 0, 0, 1, op, dummy, dummy, hp, None) == _abi.MUCA_ERR_INVALID_ARG
+        assert lib.muca_last_error(None)
+    om[3] = float("nan")
+    assert f(ctypes.byref(good), 0, 0, 1, op, dummy, dummy, hp, None) == _abi.MUCA_ERR_INVALID_ARG
+    assert b"finite" in lib.muca_last_error(None)
+    om[3] = 0.0
+    # the attempt position would pass 2^64
+    assert f(ctypes.byref(good), (1 << 64) // 16, 0, 1, op, dummy, dummy, hp, None) == _abi.MUCA_ERR_OVERFLOW
+    # the scratch holds the tables of the largest lattice
+    assert _abi.MUCA_STATIC_SCRATCH_BYTES >= 40 * (128 * 128 + 1)
+
+
 def test_null_handle_calls_are_rejected(lib):
     assert lib.muca_iterate(None, 0, 1, None) == _abi.MUCA_ERR_INVALID_ARG
     assert lib.muca_histogram(None, None, 0) == _abi.MUCA_ERR_INVALID_ARG
