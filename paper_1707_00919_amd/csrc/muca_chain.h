@@ -1,5 +1,5 @@
 // muca_chain.h -- the per-walker Metropolis chain of one row, shared by the
-// one-wave (fast) and two-wave (split) sweep kernels (L <= 64).
+// one-wave (fast), two-wave (split) and wide sweep kernels.
 //
 // One lane runs one walker; all lanes of a wave are on the same site
 // (typewriter order, Sec. 2.3).  The walker's energy bin k is kept as the byte
@@ -14,8 +14,10 @@
 // thresholds attempt x+1 can need -- site x kept, or site x flipped (which
 // moves the bin and the left-neighbour bond of site x+1) -- are already
 // loading; after the compare the step picks one.  The bin an attempt leaves
-// the walker in is counted one attempt later, after the next loads are
-// issued, since LDS answers a wave's requests in order.
+// the walker in is counted either by the chain itself, one attempt later
+// (after the next loads are issued, since LDS answers a wave's requests in
+// order), or by a second wave from bins the chain hands over in LDS (the
+// Count policies below).  The row bookkeeping is in muca_rowbits.h.
 //
 // Where the records live is a Records policy: LdsRecords (28-byte records in
 // LDS, counter inside, L <= 64) or GlobalRecords (32-byte threshold records in
@@ -113,15 +115,47 @@ struct PhiloxDraws {
     }
 };
 
+// Where the bins the attempts leave the walker in are counted.  InlineCount:
+// the chain adds each to its bin's LDS counter itself, one attempt late
+// (after the next threshold loads are issued).  RingCount: the chain stores
+// them, four per 16-byte store, in an LDS ring slot of the loop step --
+// [block of four attempts][64 lanes] x 16 bytes -- and a second wave of the
+// workgroup adds them to the counters (the two-wave kernel, where its LDS
+// has room for the ring).
+struct InlineCount {
+    static constexpr bool kInline = true;
+    template <int P>
+    __device__ __forceinline__ void after(uint32_t)
+    {
+    }
+};
+
+struct RingCount {
+    static constexpr bool kInline = false;
+    uint8_t* slot;
+    uint32_t lane;
+    uint32_t zs[4];
+    template <int P>
+    __device__ __forceinline__ void after(uint32_t z)
+    {
+        zs[P & 3] = z;
+        if constexpr ((P & 3) == 3)
+            *reinterpret_cast<uint4*>(slot + (uint32_t)((P >> 2) * kWave + lane) * 16u) =
+                uint4{zs[0], zs[1], zs[2], zs[3]};
+    }
+};
+
 template <int L>
 struct ChainState {
-    RowBits<L> rb;
+    RowWords<L> rb;
     uint32_t z;          // the current bin's record address (Records::z_of)
     int ms;              // (anti-aligned neighbours of the next site) - 2
     uint32_t thr_keep;   // threshold S of the next site if the previous site
     uint32_t thr_flip;   // was kept / flipped (loads may still be in flight)
     bool prev_flip;      // the previous site flipped
     uint32_t inc_last;   // record flag of the attempt that left the walker in z
+    int ms_next_keep;    // m - 2 of the site after the next one, if the next
+    int ms_next_flip;    // site is kept / flips
 };
 
 // Fills the records: five thresholds S = T - 1 (by m) from table[k*5 + m], a
@@ -162,41 +196,83 @@ __device__ __forceinline__ void chain_load(ChainState<L>& st, const uint32_t* mi
         st.rb.cur[j] = mine[(size_t)j * stride];
         st.rb.dn[j] = mine[(size_t)(WPR + j) * stride];
     }
-    st.rb.f0 = 0u;
     st.z = R::z_of((energy + 2 * L * L) >> 2);
     st.inc_last = 0u;
 }
 
-// Counts the bin of the launch's last attempt; returns the walker's energy.
-template <int L, class R>
+// Counts the bin of the launch's last attempt (counted inline); returns the
+// walker's energy.
+template <int L, class R, class C = InlineCount>
 __device__ __forceinline__ int32_t chain_finish(ChainState<L>& st, const R& recs)
 {
-    recs.count(st.z, st.inc_last);
+    if constexpr (C::kInline)
+        recs.count(st.z, st.inc_last);
     return 4 * (int32_t)R::k_of(st.z) - 2 * L * L;
+}
+
+// Rows of 16 sites or more run back to back: while row y is swept, the chain
+// forms the first site word of row y+1 and, at row y's last attempt, loads the
+// two thresholds row y+1's first site can need (row y's last site kept or
+// flipped), as for any other site.  Shorter rows start with a load.
+template <int L>
+struct Seamless {
+    static constexpr bool value = L >= 16;
+};
+
+// Before the launch's first row: its first site word, the counts of sites 0
+// and 1, and site 0's threshold (rows of 16 sites or more).
+template <int L, class R>
+__device__ __forceinline__ void chain_prime(ChainState<L>& st, const R& recs)
+{
+    if constexpr (Seamless<L>::value) {
+        uint32_t nb[RowWords<L>::WPR];
+#pragma unroll
+        for (int w = 0; w < RowWords<L>::WPR; ++w)
+            nb[w] = row_bonds<L>(st.rb.cur, w);
+        st.rb.R0next = site_word0<L>(nb, st.rb.cur[0], st.rb.up[0], st.rb.dn[0]);
+        st.ms = word_ms<0>(st.rb.R0next, false);
+        st.ms_next_keep = word_ms<1>(st.rb.R0next, false);
+        st.ms_next_flip = word_ms<1>(st.rb.R0next, true);
+        st.thr_keep = recs.thr(st.z, st.ms);
+        st.thr_flip = st.thr_keep;
+        st.prev_flip = false;
+    }
 }
 
 template <int L, class R>
 __device__ __forceinline__ void chain_row_begin(ChainState<L>& st, const R& recs)
 {
-    rowbits_begin<L>(st.rb);
-    st.ms = bond_count<L, 0>(st.rb.nb, vert_minus_two<L, 0>(st.rb));
-    st.thr_keep = recs.thr(st.z, st.ms);
-    st.thr_flip = st.thr_keep;
-    st.prev_flip = false;
+    if constexpr (Seamless<L>::value) {
+        st.rb.R[0] = st.rb.R0next;
+        rowwords_begin<L>(st.rb, false);
+    } else {
+        rowwords_begin<L>(st.rb);
+        st.ms = site_ms<L, 0>(st.rb, false);
+        st.ms_next_keep = site_ms<L, 1>(st.rb, false);
+        st.ms_next_flip = site_ms<L, 1>(st.rb, true);
+        st.thr_keep = recs.thr(st.z, st.ms);
+        st.thr_flip = st.thr_keep;
+        st.prev_flip = false;
+    }
 }
 
 // Attempt at site X = P % L; P counts the sites of the loop step.
 //
 // Order inside one attempt: first the two threshold loads that site X+1 may
-// need (they depend only on the state after site X-1) and the count of the
-// previous attempt's bin, then the threshold of site X is picked from the pair
-// loaded one attempt earlier, compared, and the state updated.  The scheduling
-// barrier keeps the compiler from moving that pick, and the wait on LDS it
-// implies, above the new loads: each load then has a whole attempt of
-// independent work to hide behind.
-template <int L, int P, class R, class Draws>
+// need (they depend only on the state after site X-1: its left bond, to site
+// X, is flipped iff site X flips now) and the inline count of the previous
+// attempt's bin; then the threshold of site X is picked from the pair loaded
+// one attempt earlier and compared; then the neighbour counts of site X+2 are
+// formed, filling the wait the compare's mask needs before the selects that
+// read it; then the state is updated.  The scheduling barriers keep the
+// compiler from moving the pick, and the wait on LDS it implies, above the
+// new loads (each load then has a whole attempt of independent work to hide
+// behind), and the counts between the compare and the selects.  For the last
+// site, the right bond (to site 0) already carries site 0's flip
+// (rowwords_note_first).
+template <int L, int P, class R, class Draws, class C>
 __device__ __forceinline__ void chain_attempt(ChainState<L>& st, Words4& rc, Words4& rn, Draws& draws,
-                                              const R& recs, uint32_t inc)
+                                              const R& recs, C& cnt, uint32_t inc)
 {
     using S = ChainShape<L>;
     constexpr int X = P % L;
@@ -205,50 +281,45 @@ __device__ __forceinline__ void chain_attempt(ChainState<L>& st, Words4& rc, Wor
     if constexpr ((P >> 2) + 1 < S::BLOCKS)
         draws.template advance<(P >> 2) + 1, (P & 3)>(rn);
     const uint32_t r = rc.w[P & 3];
-    uint32_t nbf[S::WPR];
-#pragma unroll
-    for (int w = 0; w < S::WPR; ++w)
-        nbf[w] = st.rb.nb[w];
-    bond_flip<L, X>(nbf);
     const uint32_t zf = st.z - (uint32_t)(st.ms * (int)R::STRIDE);
-    int ms_keep = 0, ms_flip = 0;
+    const int ms_keep = st.ms_next_keep, ms_flip = st.ms_next_flip;
     uint32_t next_keep = 0u, next_flip = 0u;
-    if constexpr (X + 1 < L) {
-        // both possible thresholds of site X+1.  Its bonds are X (to site X,
-        // changed only if site X flips now) and X+1 (to site X+2, not yet
-        // visited in this row -- or, for the last site, to site 0, which
-        // flipped iff f0): both follow from the row-start bond word, so the
-        // counts do not wait for the previous compare.
-        uint32_t nbk[S::WPR];
-#pragma unroll
-        for (int w = 0; w < S::WPR; ++w)
-            nbk[w] = st.rb.nb0[w];
-        if constexpr (X + 2 == L)
-            nbk[(L - 1) >> 5] ^= st.rb.f0 << ((L - 1) & 31);
-        uint32_t nbkf[S::WPR];
-#pragma unroll
-        for (int w = 0; w < S::WPR; ++w)
-            nbkf[w] = nbk[w];
-        bond_flip<L, X>(nbkf);
-        const int v1 = vert_minus_two<L, X + 1>(st.rb);
-        ms_keep = bond_count<L, X + 1>(nbk, v1);
-        ms_flip = bond_count<L, X + 1>(nbkf, v1);
+    constexpr bool SEAM = Seamless<L>::value;
+    // the next site: X+1 of this row, or (seamless rows) site 0 of the next
+    if constexpr (X + 1 < L || SEAM) {
         next_keep = recs.thr(st.z, ms_keep);
         next_flip = recs.thr(zf, ms_flip);
     }
-    recs.count(st.z, X == 0 ? st.inc_last : inc);
+    if constexpr (C::kInline)
+        recs.count(st.z, X == 0 ? st.inc_last : inc);
     __builtin_amdgcn_sched_barrier(0);
     const uint32_t thr = st.prev_flip ? st.thr_flip : st.thr_keep;
     const bool accept = r <= thr;
+    __builtin_amdgcn_sched_barrier(0);
+    // the site after the next one; the next row's first sites do not
+    // neighbour this row's last one, so only site 1's left bond depends on
+    // the branch
+    if constexpr (SEAM && X + 3 == L)
+        rowwords_prepare_next<L>(st.rb);
+    if constexpr (X + 2 < L) {
+        st.ms_next_keep = site_ms<L, X + 2>(st.rb, false);
+        st.ms_next_flip = site_ms<L, X + 2>(st.rb, true);
+    } else if constexpr (SEAM && X + 2 == L) {
+        st.ms_next_keep = word_ms<0>(st.rb.R0next, false);
+        st.ms_next_flip = st.ms_next_keep;
+    } else if constexpr (SEAM && X + 1 == L) {
+        st.ms_next_keep = word_ms<1>(st.rb.R0next, false);
+        st.ms_next_flip = word_ms<1>(st.rb.R0next, true);
+    }
+    __builtin_amdgcn_sched_barrier(0);
     st.z = accept ? zf : st.z;
-#pragma unroll
-    for (int w = 0; w < S::WPR; ++w)
-        st.rb.nb[w] = accept ? nbf[w] : st.rb.nb[w];
+    cnt.template after<P>(st.z);
+    rowwords_note<L, X>(st.rb, accept);
     if constexpr (X == 0)
-        st.rb.f0 = accept ? 1u : 0u;
+        rowwords_note_first<L>(st.rb, accept);
     if constexpr (X + 1 == L)
         st.inc_last = inc;
-    if constexpr (X + 1 < L) {
+    if constexpr (X + 1 < L || SEAM) {
         st.ms = accept ? ms_flip : ms_keep;
         st.thr_keep = next_keep;
         st.thr_flip = next_flip;
@@ -256,35 +327,36 @@ __device__ __forceinline__ void chain_attempt(ChainState<L>& st, Words4& rc, Wor
     }
 }
 
-template <int L, int RR, class R, class Draws, int... Xs>
+template <int L, int RR, class R, class Draws, class C, int... Xs>
 __device__ __forceinline__ void chain_row_sites(ChainState<L>& st, Words4& rc, Words4& rn, Draws& draws,
-                                                const R& recs, uint32_t inc, std::integer_sequence<int, Xs...>)
+                                                const R& recs, C& cnt, uint32_t inc,
+                                                std::integer_sequence<int, Xs...>)
 {
-    (chain_attempt<L, RR * L + Xs>(st, rc, rn, draws, recs, inc), ...);
+    (chain_attempt<L, RR * L + Xs>(st, rc, rn, draws, recs, cnt, inc), ...);
 }
 
 // Row RR of a loop step that starts at row y: prefetch row y+RR+2, run the
 // row's L attempts, write the row back and slide the window down by one.
-template <int L, int RR, class R, class Draws>
+template <int L, int RR, class R, class Draws, class C>
 __device__ __forceinline__ void chain_row(ChainState<L>& st, Words4& rc, Words4& rn, Draws& draws,
-                                          const R& recs, uint32_t inc, uint32_t* mine, size_t stride, int y)
+                                          const R& recs, C& cnt, uint32_t inc, uint32_t* mine, size_t stride,
+                                          int y)
 {
     constexpr int WPR = ChainShape<L>::WPR;
     const int yy = y + RR;
     const int ynext = (yy + 2) % L;
-    uint32_t nx[WPR];
 #pragma unroll
     for (int j = 0; j < WPR; ++j)
-        nx[j] = mine[(size_t)(ynext * WPR + j) * stride];
+        st.rb.nx[j] = mine[(size_t)(ynext * WPR + j) * stride];
     chain_row_begin<L>(st, recs);
-    chain_row_sites<L, RR>(st, rc, rn, draws, recs, inc, std::make_integer_sequence<int, L>{});
-    rowbits_end<L>(st.rb);
+    chain_row_sites<L, RR>(st, rc, rn, draws, recs, cnt, inc, std::make_integer_sequence<int, L>{});
+    rowwords_end<L>(st.rb);
 #pragma unroll
     for (int j = 0; j < WPR; ++j) {
         mine[(size_t)(yy * WPR + j) * stride] = st.rb.cur[j];
         st.rb.up[j] = st.rb.cur[j];
         st.rb.cur[j] = st.rb.dn[j];
-        st.rb.dn[j] = nx[j];
+        st.rb.dn[j] = st.rb.nx[j];
     }
 }
 
