@@ -39,9 +39,11 @@ from muca_inputs import WORKLOADS  # noqa: E402
 WORKLOAD = "ising_L32_W16384"
 METRIC = "spin-flip attempts/s at L=32, 16384 walkers; p50/p99 time-to-converged-weights"
 
-# MI355X: 256 CUs x 4 SIMDs x 16 lanes at 2.4 GHz = full-rate 32-bit VALU
-# lane-operations per second.  On gfx950 the 32-bit integer multiplies
-# (lo, hi and the 32x32->64 mad) issue at the same rate as an add.
+# MI355X: 256 CUs x 4 SIMDs x 16 lanes at 2.4 GHz = one wave64 32-bit VALU
+# instruction per SIMD every 4 clocks, in lane-operations per second.  Measured
+# on gfx950 (bench.py --issue-probe): the 32-bit multiplies (lo, hi, the
+# 32x32->64 mad) and the three-input xor issue at 0.94-0.98 of it with eight
+# waves per SIMD; a 32-bit add issues faster (up to 1.5x).
 VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
 # Algorithmic 32-bit integer operations per attempt: a quarter of a
 # Philox4x32-10 block (5 products 32x32->64 and 10 two-input XORs; the key
@@ -52,8 +54,13 @@ ALU_OPS_PER_ATTEMPT = 5 + 10 + 13
 # The second roof: LDS bytes per attempt the chain needs -- the threshold
 # gather (4 B) and the histogram counter's read-modify-write (4 + 4 B) -- plus
 # the random words handed over through LDS in the two-wave form (4 B written,
-# 4 B read).  Peak: 128 B per clock per CU.
+# 4 B read) and, there for L <= 32, the bins handed to the counting wave (4 B
+# written, 4 B read).  Peak: 128 B per clock per CU.
 LDS_BYTES_PER_ATTEMPT = {2: 4 + 8 + 8, 1: 4 + 8, 0: 8 + 8, 3: 8, 4: 8 + 8}
+
+
+def lds_bytes_per_attempt(variant, L):
+    return LDS_BYTES_PER_ATTEMPT[variant] + (8 if variant == 2 and L <= 32 else 0)
 LDS_PEAK_BYTES = 256 * 128 * 2.4e9
 
 
@@ -273,6 +280,11 @@ def cpu_baseline(wl, ln_g, sweeps, warm, nthreads=0):
 
 # ------------------------------------------------------------ other workloads
 def _solo_solve(Solver, L, W, seed, iter_sweeps, min_flat, max_it, prod_therm, prod_sweeps):
+    """One instance alone: weight iterations to the flatness bound, then the
+    production run in one call; returns (attempts, iterations, ln g, wall s)."""
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
     s = Solver(L, W, seed)
     att, it = 0, 0
     while it < max_it:
@@ -284,7 +296,8 @@ def _solo_solve(Solver, L, W, seed, iter_sweeps, min_flat, max_it, prod_therm, p
     att += s.production(prod_therm, prod_sweeps)["attempts"]
     lng = _log_dos_or_zeros(s)
     s.close()
-    return att, it, lng
+    torch.cuda.synchronize()
+    return att, it, lng, time.perf_counter() - t0
 
 
 def _log_dos_or_zeros(s):
@@ -293,6 +306,66 @@ def _log_dos_or_zeros(s):
         return s.log_dos(0)
     except MucaError:
         return np.zeros(s.N + 1)
+
+
+def batched_solve(Batch, Solver, inst, flags, iter_sweeps, min_flat, max_it, prod_therm, prod_sweeps):
+    """The instances solved together in batched rounds.  Every round runs, for
+    each member, a weight iteration until its flatness bound, then slices of
+    its production run (at most iter_sweeps sweeps each, the unrecorded ones
+    first) from the next round on, so that early members do not wait for the
+    slowest one.  The slices' histograms are summed and ln g taken from the
+    sum (ln g(E_min) = ln 2), which equals one production call of the same
+    sweeps.  Returns (attempts, iterations, ln g list, rounds, device ms)."""
+    from paper_1707_00919_amd import MucaError
+    from paper_1707_00919_amd.analysis import jackknife_log_dos
+    members = [Solver(L, W, sd) for L, W, sd in inst]
+    b = Batch(members, flags=flags)
+    n = len(members)
+    iters = [0] * n
+    phase = [0] * n              # 0 iterating, 1 production, 2 done
+    therm_left = [prod_therm] * n
+    prod_left = [prod_sweeps] * n
+    acc = [np.zeros(m.N + 1, dtype=np.uint64) for m in members]
+    att, kernel_ms, rounds = 0, 0.0, 0
+    while any(ph != 2 for ph in phase):
+        mode = np.zeros(n, dtype=np.uint32)
+        th = np.zeros(n, dtype=np.uint32)
+        sw = np.zeros(n, dtype=np.uint32)
+        for i in range(n):
+            if phase[i] == 0:
+                mode[i], sw[i] = 1, iter_sweeps
+            elif phase[i] == 1:
+                mode[i] = 2
+                th[i] = min(therm_left[i], iter_sweeps)
+                sw[i] = min(prod_left[i], iter_sweeps - th[i])
+        infos = b.run(mode, th, sw)
+        rounds += 1
+        kernel_ms += next(i for i in infos if i is not None)["kernel_ms"]
+        for i, inf in enumerate(infos):
+            if inf is None:
+                continue
+            att += inf["attempts"]
+            if phase[i] == 0:
+                iters[i] += 1
+                if inf["flatness"] >= min_flat or iters[i] >= max_it:
+                    phase[i] = 1
+            else:
+                therm_left[i] -= int(th[i])
+                prod_left[i] -= int(sw[i])
+                if sw[i]:
+                    acc[i] += members[i].histogram()
+                if therm_left[i] == 0 and prod_left[i] == 0:
+                    phase[i] = 2
+    lngs = []
+    for m, h in zip(members, acc):
+        try:
+            lngs.append(jackknife_log_dos(m.L, h, m.log_weights(), normalization=0)[0])
+        except MucaError:
+            lngs.append(np.zeros(m.N + 1))
+    b.close()
+    for m in members:
+        m.close()
+    return att, iters, lngs, rounds, kernel_ms
 
 
 def bench_batched(args):
@@ -305,33 +378,8 @@ def bench_batched(args):
     flags = _abi.MUCA_BATCH_GRAPH | _abi.MUCA_BATCH_AUTOTUNE
 
     def batched():
-        members = [Solver(L, W, sd) for L, W, sd in inst]
-        b = Batch(members, flags=flags)
-        n = len(members)
-        iters = [0] * n
-        done = [False] * n
-        att = 0
-        kernel_ms = 0.0
-        rounds = 0
-        while not all(done):
-            infos = b.run([0 if d else 1 for d in done], 0, C["iter_sweeps"])
-            rounds += 1
-            kernel_ms += next(i for i in infos if i is not None)["kernel_ms"]
-            for i, inf in enumerate(infos):
-                if inf is None:
-                    continue
-                att += inf["attempts"]
-                iters[i] += 1
-                if inf["flatness"] >= C["min_flat"] or iters[i] >= C["max_iterations"]:
-                    done[i] = True
-        infos = b.run([2] * n, C["prod_therm_sweeps"], C["prod_sweeps"])
-        kernel_ms += infos[0]["kernel_ms"]
-        att += sum(i["attempts"] for i in infos)
-        lngs = [_log_dos_or_zeros(m) for m in members]
-        b.close()
-        for m in members:
-            m.close()
-        return att, iters, lngs, rounds, kernel_ms
+        return batched_solve(Batch, Solver, inst, flags, C["iter_sweeps"], C["min_flat"], C["max_iterations"],
+                             C["prod_therm_sweeps"], C["prod_sweeps"])
 
     for _ in range(args.warmup):
         batched()
@@ -343,16 +391,19 @@ def bench_batched(args):
     print("batched: %.2f s, %d rounds" % (wall_b, rounds), file=sys.stderr, flush=True)
     t0 = time.perf_counter()
     att_s, same = 0, True
-    iters_s = []
+    iters_s, solo_wall = [], []
     for (L, W, sd), lb in zip(inst, lng_b):
-        a, it, lng = _solo_solve(Solver, L, W, sd, C["iter_sweeps"], C["min_flat"],
-                                 C["max_iterations"], C["prod_therm_sweeps"], C["prod_sweeps"])
+        a, it, lng, ws = _solo_solve(Solver, L, W, sd, C["iter_sweeps"], C["min_flat"],
+                                     C["max_iterations"], C["prod_therm_sweeps"], C["prod_sweeps"])
         att_s += a
         iters_s.append(it)
+        solo_wall.append(ws)
         same &= bool(np.array_equal(lng.view(np.uint64), lb.view(np.uint64)))
     torch.cuda.synchronize()
     wall_s = time.perf_counter() - t0
-    print("one per launch: %.2f s" % wall_s, file=sys.stderr, flush=True)
+    slow = int(np.argmax(solo_wall))
+    print("one per launch: %.2f s; slowest member alone %.2f s (L=%d, %d walkers)" %
+          (wall_s, solo_wall[slow], inst[slow][0], inst[slow][1]), file=sys.stderr, flush=True)
     out = {
         "metric": "aggregate spin-flip attempts/s, 48 uneven instances, batched rounds",
         "value": att_b / wall_b, "unit": "attempts/s", "n_gpus": 1, "steps": 1,
@@ -363,12 +414,17 @@ def bench_batched(args):
                    "walkers_total": sum(W for _, W, _ in inst),
                    "iter_sweeps": C["iter_sweeps"], "min_flatness": C["min_flat"],
                    "production": [C["prod_therm_sweeps"], C["prod_sweeps"]],
+                   "production_slices": C["iter_sweeps"],
                    "batch_flags": "graph|autotune"},
         "one_per_launch_attempts_per_s": att_s / wall_s,
         "speedup_vs_one_per_launch": (att_b / wall_b) / (att_s / wall_s),
         "bit_identical_to_one_per_launch": same and iters_b == iters_s,
         "rounds": rounds, "iterations_max": max(iters_b),
         "batched_wall_s": wall_b, "one_per_launch_wall_s": wall_s,
+        "slowest_member_alone_s": solo_wall[slow],
+        "slowest_member": {"L": inst[slow][0], "walkers": inst[slow][1], "seed": inst[slow][2],
+                           "iterations": iters_s[slow]},
+        "makespan_over_slowest_alone": wall_b / solo_wall[slow],
         "batched_device_ms": kms,
     }
     print(json.dumps(out), flush=True)
@@ -424,7 +480,7 @@ def bench_served(args):
         att_s, same = 0, True
         for i in range(min(args.serve_solo_sample, len(reqs))):
             _, L, W, sd = reqs[i]
-            a, _, lng = _solo_solve(Solver, L, W, sd, Q["iter_sweeps"], Q["min_flatness"],
+            a, _, lng, _ = _solo_solve(Solver, L, W, sd, Q["iter_sweeps"], Q["min_flatness"],
                                     Q["max_iterations"], Q["prod_therm"], Q["prod_sweeps"])
             att_s += a
             same &= bool(np.array_equal(lng.view(np.uint64), lng_served[i].view(np.uint64)))
@@ -767,10 +823,11 @@ def main():
             "ops_per_attempt": ALU_OPS_PER_ATTEMPT,
         },
     }
-    lds_rate = LDS_BYTES_PER_ATTEMPT[main_variant] * attempts_per_launch / avg_launch_s
+    lds_b = lds_bytes_per_attempt(main_variant, wl["L"])
+    lds_rate = lds_b * attempts_per_launch / avg_launch_s
     out["roofline_lds"] = {"achieved": lds_rate / 1e12, "peak": LDS_PEAK_BYTES / 1e12, "unit": "TB/s",
                            "frac": lds_rate / LDS_PEAK_BYTES,
-                           "bytes_per_attempt": LDS_BYTES_PER_ATTEMPT[main_variant]}
+                           "bytes_per_attempt": lds_b}
     if not args.no_hardware_rate and ln_g is not None:
         rate, ms = hardware_rate(Solver, wl, ln_g)
         out["exact_weights_attempts_per_s"] = rate

@@ -254,3 +254,37 @@ def test_batch_member_with_zero_threshold_runs_generic():
     solo[2].iterate(1, 2)
     for a, b in zip(solo, grouped):
         same(a, b)
+
+
+def test_batched_solves_with_sliced_production_match_oracle():
+    # the benchmark's batched solve (bench.batched_solve): weight iterations to
+    # the flatness bound, then the production run in slices from the round
+    # after each member's last iteration, ln g from the summed slices -- each
+    # member's iteration count and ln g bits equal the oracle's single solve
+    # (Sec. 2.2 and Eq. 4; Sec. 3.3)
+    import os
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    import bench
+    from paper_1707_00919_amd import Batch, Solver, _abi
+    inst = [(8, 64, 21), (12, 100, 22), (16, 70, 23), (8, 200, 24)]
+    it_sw, flat, max_it, p_th, p_sw = 20, 0.3, 25, 30, 50
+    note("batched solves with sliced production vs oracle")
+    att, iters, lngs, rounds, _ = bench.batched_solve(
+        Batch, Solver, inst, _abi.MUCA_BATCH_GRAPH, it_sw, flat, max_it, p_th, p_sw)
+    for (L, W, seed), it, lng in zip(inst, iters, lngs):
+        o = oracle.OracleMuca(L, W, seed)
+        oit = 0
+        while oit < max_it:
+            info = o.iterate(0, it_sw)
+            oit += 1
+            if info["flatness"] >= flat:
+                break
+        o.production(p_th, p_sw)
+        ref = o.log_dos(0)
+        assert it == oit, (L, W, seed)
+        ref = np.zeros(L * L + 1) if ref is None else ref
+        np.testing.assert_array_equal(bits(lng), bits(ref))
+    # production slices of at most it_sw sweeps: at least (p_th + p_sw) / it_sw
+    # rounds after the last member's last iteration
+    assert rounds >= max(iters) + (p_th + p_sw + it_sw - 1) // it_sw
+    assert att == sum(W * L * L * (it_sw * it + p_th + p_sw) for (L, W, _), it in zip(inst, iters))
