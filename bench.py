@@ -54,13 +54,12 @@ ALU_OPS_PER_ATTEMPT = 5 + 10 + 13
 # The second roof: LDS bytes per attempt the chain needs -- the threshold
 # gather (4 B) and the histogram counter's read-modify-write (4 + 4 B) -- plus
 # the random words handed over through LDS in the two-wave form (4 B written,
-# 4 B read) and, there for L <= 32, the bins handed to the counting wave (4 B
-# written, 4 B read).  Peak: 128 B per clock per CU.
+# 4 B read).  Peak: 128 B per clock per CU.
 LDS_BYTES_PER_ATTEMPT = {2: 4 + 8 + 8, 1: 4 + 8, 0: 8 + 8, 3: 8, 4: 8 + 8}
 
 
 def lds_bytes_per_attempt(variant, L):
-    return LDS_BYTES_PER_ATTEMPT[variant] + (8 if variant == 2 and L <= 32 else 0)
+    return LDS_BYTES_PER_ATTEMPT[variant]
 LDS_PEAK_BYTES = 256 * 128 * 2.4e9
 
 

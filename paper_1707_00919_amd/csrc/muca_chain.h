@@ -14,10 +14,9 @@
 // thresholds attempt x+1 can need -- site x kept, or site x flipped (which
 // moves the bin and the left-neighbour bond of site x+1) -- are already
 // loading; after the compare the step picks one.  The bin an attempt leaves
-// the walker in is counted either by the chain itself, one attempt later
-// (after the next loads are issued, since LDS answers a wave's requests in
-// order), or by a second wave from bins the chain hands over in LDS (the
-// Count policies below).  The row bookkeeping is in muca_rowbits.h.
+// the walker in is counted one attempt later, after the next loads are
+// issued, since LDS answers a wave's requests in order.  The row bookkeeping
+// is in muca_rowbits.h.
 //
 // Where the records live is a Records policy: LdsRecords (28-byte records in
 // LDS, counter inside, L <= 64) or GlobalRecords (32-byte threshold records in
@@ -115,36 +114,6 @@ struct PhiloxDraws {
     }
 };
 
-// Where the bins the attempts leave the walker in are counted.  InlineCount:
-// the chain adds each to its bin's LDS counter itself, one attempt late
-// (after the next threshold loads are issued).  RingCount: the chain stores
-// them, four per 16-byte store, in an LDS ring slot of the loop step --
-// [block of four attempts][64 lanes] x 16 bytes -- and a second wave of the
-// workgroup adds them to the counters (the two-wave kernel, where its LDS
-// has room for the ring).
-struct InlineCount {
-    static constexpr bool kInline = true;
-    template <int P>
-    __device__ __forceinline__ void after(uint32_t)
-    {
-    }
-};
-
-struct RingCount {
-    static constexpr bool kInline = false;
-    uint8_t* slot;
-    uint32_t lane;
-    uint32_t zs[4];
-    template <int P>
-    __device__ __forceinline__ void after(uint32_t z)
-    {
-        zs[P & 3] = z;
-        if constexpr ((P & 3) == 3)
-            *reinterpret_cast<uint4*>(slot + (uint32_t)((P >> 2) * kWave + lane) * 16u) =
-                uint4{zs[0], zs[1], zs[2], zs[3]};
-    }
-};
-
 template <int L>
 struct ChainState {
     RowWords<L> rb;
@@ -200,13 +169,11 @@ __device__ __forceinline__ void chain_load(ChainState<L>& st, const uint32_t* mi
     st.inc_last = 0u;
 }
 
-// Counts the bin of the launch's last attempt (counted inline); returns the
-// walker's energy.
-template <int L, class R, class C = InlineCount>
+// Counts the bin of the launch's last attempt; returns the walker's energy.
+template <int L, class R>
 __device__ __forceinline__ int32_t chain_finish(ChainState<L>& st, const R& recs)
 {
-    if constexpr (C::kInline)
-        recs.count(st.z, st.inc_last);
+    recs.count(st.z, st.inc_last);
     return 4 * (int32_t)R::k_of(st.z) - 2 * L * L;
 }
 
@@ -270,9 +237,9 @@ __device__ __forceinline__ void chain_row_begin(ChainState<L>& st, const R& recs
 // behind), and the counts between the compare and the selects.  For the last
 // site, the right bond (to site 0) already carries site 0's flip
 // (rowwords_note_first).
-template <int L, int P, class R, class Draws, class C>
+template <int L, int P, class R, class Draws>
 __device__ __forceinline__ void chain_attempt(ChainState<L>& st, Words4& rc, Words4& rn, Draws& draws,
-                                              const R& recs, C& cnt, uint32_t inc)
+                                              const R& recs, uint32_t inc)
 {
     using S = ChainShape<L>;
     constexpr int X = P % L;
@@ -290,8 +257,7 @@ __device__ __forceinline__ void chain_attempt(ChainState<L>& st, Words4& rc, Wor
         next_keep = recs.thr(st.z, ms_keep);
         next_flip = recs.thr(zf, ms_flip);
     }
-    if constexpr (C::kInline)
-        recs.count(st.z, X == 0 ? st.inc_last : inc);
+    recs.count(st.z, X == 0 ? st.inc_last : inc);
     __builtin_amdgcn_sched_barrier(0);
     const uint32_t thr = st.prev_flip ? st.thr_flip : st.thr_keep;
     const bool accept = r <= thr;
@@ -313,7 +279,6 @@ __device__ __forceinline__ void chain_attempt(ChainState<L>& st, Words4& rc, Wor
     }
     __builtin_amdgcn_sched_barrier(0);
     st.z = accept ? zf : st.z;
-    cnt.template after<P>(st.z);
     rowwords_note<L, X>(st.rb, accept);
     if constexpr (X == 0)
         rowwords_note_first<L>(st.rb, accept);
@@ -327,29 +292,27 @@ __device__ __forceinline__ void chain_attempt(ChainState<L>& st, Words4& rc, Wor
     }
 }
 
-template <int L, int RR, class R, class Draws, class C, int... Xs>
+template <int L, int RR, class R, class Draws, int... Xs>
 __device__ __forceinline__ void chain_row_sites(ChainState<L>& st, Words4& rc, Words4& rn, Draws& draws,
-                                                const R& recs, C& cnt, uint32_t inc,
-                                                std::integer_sequence<int, Xs...>)
+                                                const R& recs, uint32_t inc, std::integer_sequence<int, Xs...>)
 {
-    (chain_attempt<L, RR * L + Xs>(st, rc, rn, draws, recs, cnt, inc), ...);
+    (chain_attempt<L, RR * L + Xs>(st, rc, rn, draws, recs, inc), ...);
 }
 
 // Row RR of a loop step that starts at row y: prefetch row y+RR+2, run the
 // row's L attempts, write the row back and slide the window down by one.
-template <int L, int RR, class R, class Draws, class C>
+template <int L, int RR, class R, class Draws>
 __device__ __forceinline__ void chain_row(ChainState<L>& st, Words4& rc, Words4& rn, Draws& draws,
-                                          const R& recs, C& cnt, uint32_t inc, uint32_t* mine, size_t stride,
-                                          int y)
+                                          const R& recs, uint32_t inc, uint32_t* mine, size_t stride, int y)
 {
     constexpr int WPR = ChainShape<L>::WPR;
-    const int yy = y + RR;
-    const int ynext = (yy + 2) % L;
+    const uint32_t yy = (uint32_t)(y + RR);
+    const uint32_t ynext = yy + 2u < (uint32_t)L ? yy + 2u : yy + 2u - (uint32_t)L;
 #pragma unroll
     for (int j = 0; j < WPR; ++j)
         st.rb.nx[j] = mine[(size_t)(ynext * WPR + j) * stride];
     chain_row_begin<L>(st, recs);
-    chain_row_sites<L, RR>(st, rc, rn, draws, recs, cnt, inc, std::make_integer_sequence<int, L>{});
+    chain_row_sites<L, RR>(st, rc, rn, draws, recs, inc, std::make_integer_sequence<int, L>{});
     rowwords_end<L>(st.rb);
 #pragma unroll
     for (int j = 0; j < WPR; ++j) {

@@ -79,15 +79,11 @@ constexpr uint32_t kLdsPerCu = 160u * 1024u;
 // LDS bytes of one workgroup of the fast sweep (a 28-byte record per energy
 // bin) and of the split sweep (the records, rounded up to 16 bytes so that
 // the ring's 16-byte accesses are aligned, plus a two-slot ring of Philox
-// words, one loop step of 64 walkers per slot, and for L <= 32 a two-slot ring
-// of the chain's bins of the same size).
+// words, one loop step of 64 walkers per slot).
 __host__ __device__ constexpr uint32_t fast_lds_bytes(uint32_t L) { return 28u * (L * L + 1u); }
 __host__ __device__ constexpr uint32_t split_lds_bytes(uint32_t L)
 {
-    // for L <= 32 a second ring of the same shape hands the chain's bins to
-    // the producer wave, which counts them
-    return (28u * (L * L + 1u) + 15u) / 16u * 16u +
-           (L <= 32u ? 4u : 2u) * ((L % 4u == 0u ? 1u : 2u) * L / 4u) * (uint32_t)kWave * 16u;
+    return (28u * (L * L + 1u) + 15u) / 16u * 16u + 2u * ((L % 4u == 0u ? 1u : 2u) * L / 4u) * (uint32_t)kWave * 16u;
 }
 
 // LDS bytes of one workgroup of the two-wave sweep for L > 64: the 32-bit

@@ -41,7 +41,6 @@ __device__ __forceinline__ void fast_chain(const FastSweepArgs& a, uint32_t w, u
     chain_load<L, LdsRecords>(st, mine, stride, a.energy[w]);
     chain_prime<L>(st, recs);
     const uint32_t live = w < a.walkers ? 1u : 0u;
-    InlineCount cnt;
     for (uint32_t t = 0; t < a.nsweeps; ++t) {
         const uint64_t sweep = a.sweep0 + t;
         const uint32_t inc = t >= a.therm ? live : 0u;
@@ -49,9 +48,9 @@ __device__ __forceinline__ void fast_chain(const FastSweepArgs& a, uint32_t w, u
             PhiloxDraws draws{(uint32_t)(y * L) >> 2, (uint32_t)sweep, (uint32_t)(sweep >> 32), a.seed, w, {}};
             Words4 rn = draws.first();
             Words4 rc;
-            chain_row<L, 0>(st, rc, rn, draws, recs, cnt, inc, mine, stride, y);
+            chain_row<L, 0>(st, rc, rn, draws, recs, inc, mine, stride, y);
             if constexpr (S::RPS == 2)
-                chain_row<L, 1>(st, rc, rn, draws, recs, cnt, inc, mine, stride, y);
+                chain_row<L, 1>(st, rc, rn, draws, recs, inc, mine, stride, y);
         }
     }
     a.energy[w] = chain_finish<L>(st, recs);

@@ -40,11 +40,7 @@ struct SplitShape : ChainShape<L> {
     using C = ChainShape<L>;
     static constexpr int FRONT_BYTES = ((WIDE ? 4 * (C::N + 1) : C::REC_BYTES) + 15) / 16 * 16;
     static constexpr int SLOT_BYTES = C::BLOCKS * kWave * 16;
-    // rows of at most 32 sites: the chain hands its bins to the producer wave
-    // through a second two-slot ring of the same shape, behind the first
-    static constexpr bool ZRING = !WIDE && L <= 32;
-    static constexpr int ZRING_OFF = FRONT_BYTES + 2 * SLOT_BYTES;
-    static constexpr int LDS_BYTES = FRONT_BYTES + (ZRING ? 4 : 2) * SLOT_BYTES;
+    static constexpr int LDS_BYTES = FRONT_BYTES + 2 * SLOT_BYTES;
 };
 
 // The consumer's random words: one 16-byte load per block from the ring slot
@@ -88,29 +84,6 @@ __device__ __forceinline__ void produce_step(uint8_t* lds, uint32_t s, const Fas
     }
 }
 
-// Producer: the bins the chain left its walkers in during loop step s (ring
-// slot s & 1), each added to its bin's LDS counter if the step's sweep is
-// recorded and the walker is not padding.
-template <int L>
-__device__ __forceinline__ void count_step(uint8_t* lds, uint32_t s, const FastSweepArgs& a, uint32_t live,
-                                           uint32_t lane)
-{
-    using S = SplitShape<L, false>;
-    const uint32_t t = s / S::STEPS;
-    if (t < a.therm || !live)
-        return;
-    const LdsRecords recs{lds};
-    const uint8_t* slot = lds + S::ZRING_OFF + (s & 1u) * S::SLOT_BYTES;
-#pragma unroll 2
-    for (int b = 0; b < S::BLOCKS; ++b) {
-        const uint4 z = *reinterpret_cast<const uint4*>(slot + (uint32_t)(b * kWave + lane) * 16u);
-        recs.count(z.x, 1u);
-        recs.count(z.y, 1u);
-        recs.count(z.z, 1u);
-        recs.count(z.w, 1u);
-    }
-}
-
 template <int L, bool WIDE>
 __device__ __forceinline__ void sweep_split_kernel_body(const FastSweepArgs& a, uint32_t block)
 {
@@ -123,7 +96,7 @@ __device__ __forceinline__ void sweep_split_kernel_body(const FastSweepArgs& a, 
     uint32_t* const counters = reinterpret_cast<uint32_t*>(lds);  // wide form
 
     const uint32_t lane = threadIdx.x & (kWave - 1);
-    // wave 0: chain; wave 1: random numbers (and, for L <= 32, the counts).
+    // wave 0: chain; wave 1: random numbers.
     // The test is made wave-uniform so that each wave takes one branch as a
     // whole and the loop's step arithmetic stays scalar.
     const bool consumer = __builtin_amdgcn_readfirstlane(threadIdx.x) < kWave;
@@ -154,37 +127,24 @@ __device__ __forceinline__ void sweep_split_kernel_body(const FastSweepArgs& a, 
         chain_prime<L>(st, recs);
     }
 
-    using Count = std::conditional_t<S::ZRING, RingCount, InlineCount>;
     for (uint32_t s = 0; s < steps; ++s) {
         if (consumer) {
             const uint32_t t = s / S::STEPS;
             const int y = (int)(s - t * S::STEPS) * S::RPS;
             const uint32_t inc = t >= a.therm ? live : 0u;
             RingDraws draws{lds, S::FRONT_BYTES + (s & 1u) * S::SLOT_BYTES, lane};
-            Count cnt;
-            if constexpr (S::ZRING)
-                cnt = RingCount{lds + S::ZRING_OFF + (s & 1u) * S::SLOT_BYTES, lane, {}};
             Words4 rn = draws.first();
             Words4 rc;
-            chain_row<L, 0>(st, rc, rn, draws, recs, cnt, inc, mine, stride, y);
+            chain_row<L, 0>(st, rc, rn, draws, recs, inc, mine, stride, y);
             if constexpr (S::RPS == 2)
-                chain_row<L, 1>(st, rc, rn, draws, recs, cnt, inc, mine, stride, y);
-        } else {
-            if (s + 1 < steps)
-                produce_step<L, WIDE>(lds, s + 1, a, w, lane);
-            if constexpr (S::ZRING) {
-                if (s > 0)
-                    count_step<L>(lds, s - 1, a, live, lane);
-            }
+                chain_row<L, 1>(st, rc, rn, draws, recs, inc, mine, stride, y);
+        } else if (s + 1 < steps) {
+            produce_step<L, WIDE>(lds, s + 1, a, w, lane);
         }
         __syncthreads();
     }
-    if (consumer) {
-        a.energy[w] = chain_finish<L, R, Count>(st, recs);
-    } else if constexpr (S::ZRING) {
-        if (steps > 0)
-            count_step<L>(lds, steps - 1, a, live, lane);
-    }
+    if (consumer)
+        a.energy[w] = chain_finish<L>(st, recs);
     __syncthreads();
     if constexpr (WIDE) {
         for (int k = threadIdx.x; k <= N; k += 2 * kWave) {
