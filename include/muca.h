@@ -317,15 +317,23 @@ typedef struct muca_batch muca_batch;
                                      sweep counts and kernel forms) is unchanged;
                                      rounds that need several launches per member
                                      run without the graph                     */
-#define MUCA_BATCH_AUTOTUNE 0x2u  /* time four launch shapes on the first four
-                                     rounds and keep the fastest: the two-wave
-                                     form, the one-wave form with its default
-                                     walkers per workgroup, the one-wave form
-                                     with 256 walkers (four waves) sharing each
-                                     threshold table, and the default form with
+#define MUCA_BATCH_AUTOTUNE 0x2u  /* for rounds whose two-wave workgroups do
+                                     not all fit on the device at once, time
+                                     four launch shapes on four such rounds and
+                                     keep the fastest -- the mixed shape (the
+                                     two-wave form for the members with the
+                                     fewest walkers, as many as fit, the
+                                     one-wave form for the rest), the one-wave
+                                     form with its default walkers per
+                                     workgroup, the one-wave form with 256
+                                     walkers (four waves) sharing each
+                                     threshold table, and the mixed shape with
                                      the histograms merged twice per round (two
-                                     launches); results do not depend on the
-                                     choice                                    */
+                                     launches) -- and time them again once the
+                                     rounds' walkers have halved; rounds that
+                                     fit run the two-wave form, and without the
+                                     flag the others run the mixed shape;
+                                     results do not depend on the choice        */
 
 /* Group count live instances.  members[] stay owned by the caller and must
  * outlive the batch; they are not to be called while a round runs, and all

@@ -50,14 +50,20 @@ struct Group {
     uint32_t nitems = 0;
 };
 
-// The autotuner's choices: for members that can run the LDS-record kernels
-// the two-wave form, the one-wave form with its default wave groups, or the
-// one-wave form with four waves (256 walkers) sharing each table; and the
-// histogram-merge cadence -- the default form with the round's sweeps cut
-// into two launches, so that every workgroup's LDS counters are merged into
-// the global histogram twice per round instead of once.
-constexpr int kChoices = 4;
-constexpr int kTwoWave = 0, kOneWaveDefault = 1, kOneWaveFour = 2, kTwoMerges = 3;
+// Launch shapes of a round, for members that can run the LDS-record kernels:
+// the two-wave form for all; the one-wave form with its default wave groups,
+// or with four waves (256 walkers) sharing each table; the mixed shape -- the
+// two-wave form for the members with the fewest walkers, as many as fit on the
+// device at once, the one-wave form for the others; and the histogram-merge
+// cadence -- the round's default shape with its sweeps cut into two launches,
+// so that every workgroup's LDS counters are merged into the global histogram
+// twice per round instead of once.  A round whose two-wave workgroups all fit
+// runs the two-wave form; the others run the mixed shape, or with the
+// autotuner the fastest of the last four, timed on four rounds and timed again
+// once the rounds' walkers have halved since.
+constexpr int kChoices = 5;
+constexpr int kTwoWave = 0, kOneWaveDefault = 1, kOneWaveFour = 2, kTwoMerges = 3, kMixed = 4;
+constexpr int kTuned[4] = {kMixed, kOneWaveDefault, kOneWaveFour, kTwoMerges};
 
 }  // namespace
 
@@ -96,10 +102,15 @@ struct muca_batch {
     std::vector<muca_info> round_infos;
     int host_rc = MUCA_OK;
     std::string host_err;
-    // autotuner: attempts/ms of the two-wave and one-wave forms
+    // autotuner: attempts/ms of the shapes timed so far (rounds whose
+    // two-wave workgroups do not all fit)
     uint32_t round = 0;
-    double tuned_rate[kChoices] = {0.0, 0.0, 0.0, 0.0};
+    double tuned_rate[kChoices] = {0.0, 0.0, 0.0, 0.0, 0.0};
     int tuned_form = -1;
+    uint32_t tune_step = 0;        // shapes timed since the last (re)start
+    uint64_t tuned_walkers = 0;    // walkers of the round the choice was made on
+    bool tuning = false;           // the submitted round is timed for the autotuner
+    uint64_t round_walkers = 0;    // walkers of the submitted round
     int choice = kTwoWave;  // of the submitted round
     std::string err;
 };
@@ -484,8 +495,13 @@ static int muca_batch_submit_impl(muca_batch* b, const uint32_t* mode, const uin
     }
     // two-wave form while all of the batch's two-wave workgroups fit on the
     // device at once, at most two per CU (LDS shares weighted by each L)
+    std::vector<double> share(count, 0.0);
     double lds_share = 0.0;
+    uint64_t walkers = 0;
     for (uint32_t i = 0; i < count; ++i) {
+        if (mode[i] == MUCA_BATCH_SKIP)
+            continue;
+        walkers += b->m[i]->p.walkers;
         const uint32_t L = b->m[i]->L;
         uint32_t bytes = 0;
         if (form[i] == kFast && muca::split_sweep_supported(L))
@@ -493,23 +509,59 @@ static int muca_batch_submit_impl(muca_batch* b, const uint32_t* mode, const uin
         else if (form[i] == kWide && muca::wide_split_supported(L))
             bytes = muca::wide_split_lds_bytes(L);
         if (bytes)
-            lds_share += (double)(b->m[i]->wpad / muca::kWave) *
-                         std::max(0.5, 1.0 / (double)(muca::kLdsPerCu / bytes));
+            share[i] = (double)(b->m[i]->wpad / muca::kWave) * std::max(0.5, 1.0 / (double)(muca::kLdsPerCu / bytes));
+        lds_share += share[i];
     }
     const bool two_wave = active_blocks <= 2u * (uint32_t)b->cus && lds_share <= (double)b->cus;
-    b->choice = two_wave ? kTwoWave : kOneWaveDefault;
-    if (b->flags & MUCA_BATCH_AUTOTUNE)
-        b->choice = b->tuned_form >= 0 ? b->tuned_form : (int)(b->round % kChoices);
-    // the kernel form of the choice (the merge-cadence choice keeps the default form)
-    const int shape = b->choice == kTwoMerges ? (two_wave ? kTwoWave : kOneWaveDefault) : b->choice;
+    b->tuning = false;
+    b->round_walkers = walkers;
+    if (two_wave) {
+        b->choice = kTwoWave;
+    } else if (b->flags & MUCA_BATCH_AUTOTUNE) {
+        if (b->tuned_form >= 0 && 2 * walkers < b->tuned_walkers) {
+            b->tuned_form = -1;  // the rounds have thinned out: time the shapes again
+            b->tune_step = 0;
+        }
+        b->tuning = b->tuned_form < 0;
+        b->choice = b->tuning ? kTuned[b->tune_step % 4] : b->tuned_form;
+    } else {
+        b->choice = kMixed;
+    }
+    // the kernel form of the choice (the merge-cadence choice keeps the default shape)
+    const int shape = b->choice == kTwoMerges ? (two_wave ? kTwoWave : kMixed) : b->choice;
+    // members in the two-wave form: all, or (mixed) those with the fewest
+    // walkers while their workgroups fit -- a population with fewer walkers
+    // needs more weight iterations, so its chains are the ones later rounds
+    // wait for, and it costs the least room
+    std::vector<char> two(count, 0);
+    if (shape == kTwoWave) {
+        std::fill(two.begin(), two.end(), 1);
+    } else if (shape == kMixed) {
+        std::vector<uint32_t> order;
+        for (uint32_t i = 0; i < count; ++i)
+            if (mode[i] != MUCA_BATCH_SKIP && share[i] > 0.0)
+                order.push_back(i);
+        std::stable_sort(order.begin(), order.end(),
+                         [&](uint32_t x, uint32_t y) { return b->m[x]->p.walkers < b->m[y]->p.walkers; });
+        double used = 0.0;
+        size_t blocks = 0;
+        for (uint32_t i : order) {
+            const size_t nb = b->m[i]->wpad / muca::kWave;
+            if (used + share[i] > (double)b->cus || blocks + nb > 2u * (size_t)b->cus)
+                break;
+            used += share[i];
+            blocks += nb;
+            two[i] = 1;
+        }
+    }
     std::vector<uint32_t> waves(count, 1u);
     for (uint32_t i = 0; i < count; ++i) {
         const uint32_t L = b->m[i]->L;
-        if (form[i] == kWide && shape == kTwoWave && !(b->m[i]->p.flags & MUCA_FLAG_FAST_KERNEL) &&
+        if (form[i] == kWide && two[i] && !(b->m[i]->p.flags & MUCA_FLAG_FAST_KERNEL) &&
             muca::wide_split_supported(L))
             form[i] = kWideSplit;  // the same tables, Philox on a second wave
         if (form[i] == kFast) {
-            const bool want_fast = (b->m[i]->p.flags & MUCA_FLAG_FAST_KERNEL) != 0 || shape != kTwoWave;
+            const bool want_fast = (b->m[i]->p.flags & MUCA_FLAG_FAST_KERNEL) != 0 || !two[i];
             if (muca::split_sweep_supported(L) && !(want_fast && muca::fast_sweep_supported(L))) {
                 form[i] = kSplit;
             } else {
@@ -756,14 +808,15 @@ int muca_batch_finish(muca_batch* b, muca_info* infos)
             infos[i] = b->round_infos[i];
         attempts += (uint64_t)b->m[i]->p.walkers * b->m[i]->N * b->total[i];
     }
-    if (b->launches && (b->flags & MUCA_BATCH_AUTOTUNE) && b->tuned_form < 0 && ms > 0.0f) {
+    if (b->launches && b->tuning && ms > 0.0f) {
         b->tuned_rate[b->choice] = (double)attempts / ms;
-        if (b->round + 1 >= (uint32_t)kChoices) {
-            int best = 0;
-            for (int c = 1; c < kChoices; ++c)
+        if (++b->tune_step >= 4u) {
+            int best = kTuned[0];
+            for (int c : kTuned)
                 if (b->tuned_rate[c] > b->tuned_rate[best])
                     best = c;
             b->tuned_form = best;
+            b->tuned_walkers = b->round_walkers;
         }
     }
     if (b->launches)

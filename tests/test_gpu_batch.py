@@ -86,9 +86,59 @@ def test_batch_matches_solo(flags):
             assert infos[i]["sweep_counter"] == si["sweep_counter"]
     for a, b in zip(solo, grouped):
         same(a, b)
-    # the L = 96 member ran the two-wave wide form, and with the autotuner
-    # (which also tries the one-wave shapes) the one-wave wide form as well
-    assert wide_forms == ({3, 4} if flags & 2 else {4})
+    # every round's two-wave workgroups fit on the device at once, so every
+    # round runs the two-wave form, with the autotuner too: the L = 96 member
+    # ran the two-wave wide form only
+    assert wide_forms == {4}
+    batch.close()
+
+
+# a batch whose two-wave workgroups do not all fit: an L = 64 member of 257
+# waves (one 147 KB two-wave workgroup per CU) beside small members
+CROWDED = [(64, 16448, 21), (8, 300, 22), (16, 1000, 23), (96, 65, 24), (32, 130, 25)]
+CROWDED_ROUNDS = [
+    ([1] * 5, [0] * 5, [1] * 5),
+    ([2, 1, 2, 1, 2], [1, 0, 0, 1, 0], [1, 2, 1, 1, 2]),
+    ([1, 2, 0, 2, 1], [0, 1, 0, 0, 1], [2, 1, 0, 2, 1]),
+    ([2] * 5, [0] * 5, [1] * 5),
+    ([1] * 5, [1] * 5, [1] * 5),
+    ([2] * 5, [0] * 5, [2] * 5),
+]
+
+
+@pytest.mark.parametrize("flags", [0, 2])
+def test_crowded_batch_mixed_and_one_wave_shapes_match_solo(flags):
+    # without the autotuner every round runs the mixed shape (the small
+    # members two-wave, the L = 64 member one-wave); with it the first four
+    # rounds time the mixed shape, both one-wave shapes and the split-merge
+    # cadence, and later rounds keep the fastest; every member stays bit for
+    # bit equal to its solo run
+    from paper_1707_00919_amd import Batch
+    note("crowded batch flags=%d" % flags)
+    solo = make(CROWDED)
+    grouped = make(CROWDED)
+    batch = Batch(grouped, flags=flags)
+    forms = [set() for _ in CROWDED]
+    for modes, therm, sweeps in CROWDED_ROUNDS:
+        infos = batch.run(modes, therm, sweeps)
+        for i, s in enumerate(solo):
+            if modes[i] == 1:
+                si = s.iterate(therm[i], sweeps[i])
+            elif modes[i] == 2:
+                si = s.production(therm[i], sweeps[i])
+            else:
+                continue
+            forms[i].add(infos[i]["kernel_variant"])
+            assert infos[i]["hist_sum"] == si["hist_sum"]
+            assert infos[i]["flatness"] == si["flatness"]
+            assert infos[i]["sweep_counter"] == si["sweep_counter"]
+    for a, b in zip(solo, grouped):
+        same(a, b)
+    assert forms[0] == {1}  # L = 64: one-wave in every shape
+    if flags & 2:
+        assert forms[1] == {1, 2} and forms[3] == {3, 4}
+    else:
+        assert forms[1] == {2} and forms[2] == {2} and forms[3] == {4} and forms[4] == {2}
     batch.close()
 
 
