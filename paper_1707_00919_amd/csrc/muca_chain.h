@@ -237,15 +237,14 @@ __device__ __forceinline__ void chain_row_begin(ChainState<L>& st, const R& recs
 // behind), and the counts between the compare and the selects.  For the last
 // site, the right bond (to site 0) already carries site 0's flip
 // (rowwords_note_first).
-template <int L, int P, class R, class Draws>
+template <int L, int P, int BLOCKS, class R, class Draws>
 __device__ __forceinline__ void chain_attempt(ChainState<L>& st, Words4& rc, Words4& rn, Draws& draws,
                                               const R& recs, uint32_t inc)
 {
-    using S = ChainShape<L>;
     constexpr int X = P % L;
     if constexpr ((P & 3) == 0)
         rc = rn;
-    if constexpr ((P >> 2) + 1 < S::BLOCKS)
+    if constexpr ((P >> 2) + 1 < BLOCKS)
         draws.template advance<(P >> 2) + 1, (P & 3)>(rn);
     const uint32_t r = rc.w[P & 3];
     const uint32_t zf = st.z - (uint32_t)(st.ms * (int)R::STRIDE);
@@ -292,16 +291,17 @@ __device__ __forceinline__ void chain_attempt(ChainState<L>& st, Words4& rc, Wor
     }
 }
 
-template <int L, int RR, class R, class Draws, int... Xs>
+template <int L, int RR, int BLOCKS, class R, class Draws, int... Xs>
 __device__ __forceinline__ void chain_row_sites(ChainState<L>& st, Words4& rc, Words4& rn, Draws& draws,
                                                 const R& recs, uint32_t inc, std::integer_sequence<int, Xs...>)
 {
-    (chain_attempt<L, RR * L + Xs>(st, rc, rn, draws, recs, inc), ...);
+    (chain_attempt<L, RR * L + Xs, BLOCKS>(st, rc, rn, draws, recs, inc), ...);
 }
 
-// Row RR of a loop step that starts at row y: prefetch row y+RR+2, run the
-// row's L attempts, write the row back and slide the window down by one.
-template <int L, int RR, class R, class Draws>
+// Row RR of a loop step of BLOCKS Philox blocks that starts at row y: prefetch
+// row y+RR+2, run the row's L attempts, write the row back and slide the
+// window down by one.
+template <int L, int RR, int BLOCKS, class R, class Draws>
 __device__ __forceinline__ void chain_row(ChainState<L>& st, Words4& rc, Words4& rn, Draws& draws,
                                           const R& recs, uint32_t inc, uint32_t* mine, size_t stride, int y)
 {
@@ -312,7 +312,7 @@ __device__ __forceinline__ void chain_row(ChainState<L>& st, Words4& rc, Words4&
     for (int j = 0; j < WPR; ++j)
         st.rb.nx[j] = mine[(size_t)(ynext * WPR + j) * stride];
     chain_row_begin<L>(st, recs);
-    chain_row_sites<L, RR>(st, rc, rn, draws, recs, inc, std::make_integer_sequence<int, L>{});
+    chain_row_sites<L, RR, BLOCKS>(st, rc, rn, draws, recs, inc, std::make_integer_sequence<int, L>{});
     rowwords_end<L>(st.rb);
 #pragma unroll
     for (int j = 0; j < WPR; ++j) {
@@ -321,6 +321,24 @@ __device__ __forceinline__ void chain_row(ChainState<L>& st, Words4& rc, Words4&
         st.rb.cur[j] = st.rb.dn[j];
         st.rb.dn[j] = st.rb.nx[j];
     }
+}
+
+template <int L, int RPS, class R, class Draws, int... RRs>
+__device__ __forceinline__ void chain_rows_seq(ChainState<L>& st, Words4& rc, Words4& rn, Draws& draws, const R& recs,
+                                               uint32_t inc, uint32_t* mine, size_t stride, int y,
+                                               std::integer_sequence<int, RRs...>)
+{
+    (chain_row<L, RRs, RPS * L / 4>(st, rc, rn, draws, recs, inc, mine, stride, y), ...);
+}
+
+// The RPS rows y .. y+RPS-1 of one loop step; rn holds the step's first
+// Philox block.
+template <int L, int RPS, class R, class Draws>
+__device__ __forceinline__ void chain_rows(ChainState<L>& st, Words4& rc, Words4& rn, Draws& draws, const R& recs,
+                                           uint32_t inc, uint32_t* mine, size_t stride, int y)
+{
+    static_assert((RPS * L) % 4 == 0, "a loop step is whole Philox blocks");
+    chain_rows_seq<L, RPS>(st, rc, rn, draws, recs, inc, mine, stride, y, std::make_integer_sequence<int, RPS>{});
 }
 
 }  // namespace muca

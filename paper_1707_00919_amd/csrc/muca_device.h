@@ -77,20 +77,51 @@ inline uint32_t padded_walkers(uint32_t walkers) { return (walkers + kWave - 1) 
 constexpr uint32_t kLdsPerCu = 160u * 1024u;
 
 // LDS bytes of one workgroup of the fast sweep (a 28-byte record per energy
-// bin) and of the split sweep (the records, rounded up to 16 bytes so that
-// the ring's 16-byte accesses are aligned, plus a two-slot ring of Philox
-// words, one loop step of 64 walkers per slot).
+// bin).
 __host__ __device__ constexpr uint32_t fast_lds_bytes(uint32_t L) { return 28u * (L * L + 1u); }
-__host__ __device__ constexpr uint32_t split_lds_bytes(uint32_t L)
+
+// The two-wave sweep's LDS: the records (28 bytes per energy bin; in the wide
+// form, L > 64, the 32-bit counters alone), rounded up to 16 bytes so that the
+// ring's 16-byte accesses are aligned, in front of a two-slot ring holding the
+// Philox words of one loop step of `rows` rows per slot (16 bytes per block of
+// four sites per walker).
+__host__ __device__ constexpr uint32_t split_lds_bytes_for(uint32_t L, bool wide, uint32_t rows)
 {
-    return (28u * (L * L + 1u) + 15u) / 16u * 16u + 2u * ((L % 4u == 0u ? 1u : 2u) * L / 4u) * (uint32_t)kWave * 16u;
+    return ((wide ? 4u : 28u) * (L * L + 1u) + 15u) / 16u * 16u + 2u * (rows * L / 4u) * (uint32_t)kWave * 16u;
 }
 
-// LDS bytes of one workgroup of the two-wave sweep for L > 64: the 32-bit
-// histogram counters (rounded up to 16 bytes) in front of the same ring.
+// Two-wave workgroups one CU runs at once (at most two count: a third one's
+// producer wave would compete with the chains).
+__host__ __device__ constexpr uint32_t split_groups_per_cu(uint32_t bytes)
+{
+    return bytes > kLdsPerCu ? 0u : (kLdsPerCu / bytes < 2u ? kLdsPerCu / bytes : 2u);
+}
+
+// Rows per loop step of the two-wave sweep.  A step is whole rows of whole
+// Philox blocks (one row when L is a multiple of 4, else two); it takes two or
+// four times that many rows, up to 128 sites, where the longer ring slots still
+// leave as many workgroups per CU.  Each step ends in a barrier and in loop
+// bookkeeping on the chain wave, so longer steps shorten the chain.
+__host__ __device__ constexpr uint32_t split_rows_per_step(uint32_t L, bool wide)
+{
+    const uint32_t base = L % 4u == 0u ? 1u : 2u;
+    const uint32_t fit = split_groups_per_cu(split_lds_bytes_for(L, wide, base));
+    uint32_t rows = base;
+    for (uint32_t r = 2u * base; r <= 4u; r *= 2u)
+        if (L % r == 0u && r * L <= 128u && split_groups_per_cu(split_lds_bytes_for(L, wide, r)) >= fit)
+            rows = r;
+    return rows;
+}
+
+// LDS bytes of one workgroup of the split sweep (L <= 64) and of the wide
+// two-wave sweep (L > 64).
+__host__ __device__ constexpr uint32_t split_lds_bytes(uint32_t L)
+{
+    return split_lds_bytes_for(L, false, split_rows_per_step(L, false));
+}
 __host__ __device__ constexpr uint32_t wide_split_lds_bytes(uint32_t L)
 {
-    return (4u * (L * L + 1u) + 15u) / 16u * 16u + 2u * ((L % 4u == 0u ? 1u : 2u) * L / 4u) * (uint32_t)kWave * 16u;
+    return split_lds_bytes_for(L, true, split_rows_per_step(L, true));
 }
 
 // Waves (of 64 walkers each) per workgroup of the fast sweep.  The record

@@ -32,14 +32,19 @@
 namespace muca {
 namespace {
 
-// LDS of one workgroup: the records (or, in the wide form, the counters) in
-// front of two ring slots of one loop step each, which start on a 16-byte
-// boundary so that every 16-byte ring access is aligned.
+// Loop steps of split_rows_per_step(L, WIDE) rows; LDS of one workgroup: the
+// records (or, in the wide form, the counters) in front of two ring slots of
+// one loop step each, which start on a 16-byte boundary so that every 16-byte
+// ring access is aligned.
 template <int L, bool WIDE>
 struct SplitShape : ChainShape<L> {
     using C = ChainShape<L>;
+    static constexpr int RPS = (int)split_rows_per_step(L, WIDE);
+    static constexpr int STEPS = L / RPS;
+    static constexpr int BLOCKS = RPS * L / 4;
+    static_assert(STEPS * RPS == L && BLOCKS * 4 == RPS * L, "a loop step is whole rows and whole Philox blocks");
     static constexpr int FRONT_BYTES = ((WIDE ? 4 * (C::N + 1) : C::REC_BYTES) + 15) / 16 * 16;
-    static constexpr int SLOT_BYTES = C::BLOCKS * kWave * 16;
+    static constexpr int SLOT_BYTES = BLOCKS * kWave * 16;
     static constexpr int LDS_BYTES = FRONT_BYTES + 2 * SLOT_BYTES;
 };
 
@@ -127,24 +132,28 @@ __device__ __forceinline__ void sweep_split_kernel_body(const FastSweepArgs& a, 
         chain_prime<L>(st, recs);
     }
 
-    for (uint32_t s = 0; s < steps; ++s) {
-        if (consumer) {
+    // Each wave runs a loop of its own, with one barrier per loop step in
+    // both: a loop shared by the two waves would merge their paths every step
+    // and carry the chain's state across in register copies.
+    if (consumer) {
+        for (uint32_t s = 0; s < steps; ++s) {
             const uint32_t t = s / S::STEPS;
             const int y = (int)(s - t * S::STEPS) * S::RPS;
             const uint32_t inc = t >= a.therm ? live : 0u;
             RingDraws draws{lds, S::FRONT_BYTES + (s & 1u) * S::SLOT_BYTES, lane};
             Words4 rn = draws.first();
             Words4 rc;
-            chain_row<L, 0>(st, rc, rn, draws, recs, inc, mine, stride, y);
-            if constexpr (S::RPS == 2)
-                chain_row<L, 1>(st, rc, rn, draws, recs, inc, mine, stride, y);
-        } else if (s + 1 < steps) {
-            produce_step<L, WIDE>(lds, s + 1, a, w, lane);
+            chain_rows<L, S::RPS>(st, rc, rn, draws, recs, inc, mine, stride, y);
+            __syncthreads();
         }
-        __syncthreads();
-    }
-    if (consumer)
         a.energy[w] = chain_finish<L>(st, recs);
+    } else {
+        for (uint32_t s = 0; s < steps; ++s) {
+            if (s + 1 < steps)
+                produce_step<L, WIDE>(lds, s + 1, a, w, lane);
+            __syncthreads();
+        }
+    }
     __syncthreads();
     if constexpr (WIDE) {
         for (int k = threadIdx.x; k <= N; k += 2 * kWave) {

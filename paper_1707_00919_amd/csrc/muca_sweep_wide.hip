@@ -48,9 +48,7 @@ __device__ __forceinline__ void sweep_wide_kernel_body(const FastSweepArgs& a, u
             PhiloxDraws draws{(uint32_t)(y * L) >> 2, (uint32_t)sweep, (uint32_t)(sweep >> 32), a.seed, w, {}};
             Words4 rn = draws.first();
             Words4 rc;
-            chain_row<L, 0>(st, rc, rn, draws, recs, inc, mine, stride, y);
-            if constexpr (S::RPS == 2)
-                chain_row<L, 1>(st, rc, rn, draws, recs, inc, mine, stride, y);
+            chain_rows<L, S::RPS>(st, rc, rn, draws, recs, inc, mine, stride, y);
         }
     }
     a.energy[w] = chain_finish<L>(st, recs);

@@ -112,7 +112,11 @@ def test_small_workload_end_to_end():
 @pytest.mark.parametrize("L,W,seed", [(4, 64, 1), (6, 65, 2), (16, 257, 7), (30, 70, 9),
                                       (32, 4097, 11), (34, 66, 12), (48, 80, 13), (62, 65, 3),
                                       (64, 64, 14), (40, 200, 15), (44, 65, 16), (56, 130, 17),
-                                      (64, 320, 18), (48, 192, 19)])
+                                      (64, 320, 18), (48, 192, 19),
+                                      # two-wave loop steps of four rows (L = 8 ... 28) and
+                                      # of two rows (L = 36, 52, 60)
+                                      (8, 65, 20), (12, 64, 21), (20, 66, 22), (24, 70, 23),
+                                      (28, 130, 24), (36, 65, 25), (52, 64, 26), (60, 65, 27)])
 def test_kernel_variants_agree(L, W, seed):
     # split (two waves, thresholds fetched ahead), fast (one wave) and generic
     # (64-bit thresholds) sweep kernels: the same bits, and the oracle's
