@@ -4,9 +4,10 @@
 // One lane runs one walker; all lanes of a wave are on the same site
 // (typewriter order, Sec. 2.3).  The walker's energy bin k is kept as the byte
 // address z = 28k + 8 of its 28-byte LDS record (five thresholds S = T - 1
-// by the number m of anti-aligned neighbours, the bin's histogram counter, a
-// pad word): the threshold of a move with m anti-aligned neighbours is at
-// z + 4(m - 2), the target bin's record at z - 28(m - 2), the counter at z + 12.
+// by the number m of anti-aligned neighbours, from m = 4 down to m = 0, the
+// bin's histogram counter, a pad word).  A site is described by d = 2 - m,
+// the bin change if it flips: the threshold of its move is at z + 4d, the
+// target bin's record at z + 28d, the counter at z + 12.
 //
 // Each walker's chain is serial (the energy after one attempt picks the next
 // threshold), so a chain step's latency sets the pace.  The step hides the
@@ -50,16 +51,17 @@ struct ChainShape {
     static constexpr int REC_BYTES = REC * (N + 1);
 };
 
-// 28-byte records in LDS: z = 28k + 8, threshold of m at z + 4(m - 2),
-// counter at z + 12.
+// 28-byte records in LDS: z = 28k + 8, threshold of the move with bin
+// change d = 2 - m at z + 4d, counter at z + 12.
 struct LdsRecords {
-    static constexpr uint32_t STRIDE = 28;
     uint8_t* lds;
     __device__ __forceinline__ static uint32_t z_of(int k) { return 28u * (uint32_t)k + 8u; }
     __device__ __forceinline__ static int k_of(uint32_t z) { return (int)((z - 8u) / 28u); }
-    __device__ __forceinline__ uint32_t thr(uint32_t z, int ms) const
+    // the record of the bin d away
+    __device__ __forceinline__ static uint32_t target(uint32_t z, int d) { return z + (uint32_t)(d * 28); }
+    __device__ __forceinline__ uint32_t thr(uint32_t z, int d) const
     {
-        const uint32_t byte = z + (uint32_t)(ms * 4);  // in range: ms * 4 >= -8 and z >= 8
+        const uint32_t byte = z + (uint32_t)(d * 4);  // in range: d * 4 >= -8 and z >= 8
         return *reinterpret_cast<const uint32_t*>(lds + byte);
     }
     __device__ __forceinline__ void count(uint32_t z, uint32_t inc) const
@@ -68,21 +70,23 @@ struct LdsRecords {
     }
 };
 
-// 32-byte threshold records in global memory (S by m at bytes 4m of record
-// k): z = 32k, threshold of m at z + 8 + 4(m - 2); the counter of bin k is
-// word k of an LDS array, at byte z / 8.
+// 32-byte threshold records in global memory (S by m at bytes 4(4 - m) of
+// record k): z = 32k, threshold of the move with bin change d = 2 - m at
+// z + 8 + 4d; the counter of bin k is word k of an LDS array, at byte z / 8.
 struct GlobalRecords {
-    static constexpr uint32_t STRIDE = 32;
-    const uint8_t* table;
+    const uint8_t* table8;  // the table + 8 bytes
     uint8_t* counters;
     __device__ __forceinline__ static uint32_t z_of(int k) { return 32u * (uint32_t)k; }
     __device__ __forceinline__ static int k_of(uint32_t z) { return (int)(z >> 5); }
-    __device__ __forceinline__ uint32_t thr(uint32_t z, int ms) const
+    // the record of the bin d away
+    __device__ __forceinline__ static uint32_t target(uint32_t z, int d) { return z + ((uint32_t)d << 5); }
+    __device__ __forceinline__ uint32_t thr(uint32_t z, int d) const
     {
-        // the byte offset is formed in 32 bits first (8 + 4 ms >= 0), so that
-        // no wrapped negative term is ever added to the 64-bit pointer
-        const uint32_t byte = z + (uint32_t)(8 + ms * 4);
-        return *reinterpret_cast<const uint32_t*>(table + byte);
+        // z + 4d, formed in 32 bits, is never negative for a move a walker
+        // can propose (in bin 0 every site has d = 2; every other reachable
+        // bin has z >= 64), so no wrapped term is added to the 64-bit pointer
+        const uint32_t byte = z + (uint32_t)(d * 4);
+        return *reinterpret_cast<const uint32_t*>(table8 + byte);
     }
     __device__ __forceinline__ void count(uint32_t z, uint32_t inc) const
     {
@@ -118,13 +122,13 @@ template <int L>
 struct ChainState {
     RowWords<L> rb;
     uint32_t z;          // the current bin's record address (Records::z_of)
-    int ms;              // (anti-aligned neighbours of the next site) - 2
+    int d;               // 2 - (anti-aligned neighbours of the next site)
     uint32_t thr_keep;   // threshold S of the next site if the previous site
     uint32_t thr_flip;   // was kept / flipped (loads may still be in flight)
     bool prev_flip;      // the previous site flipped
     uint32_t inc_last;   // record flag of the attempt that left the walker in z
-    int ms_next_keep;    // m - 2 of the site after the next one, if the next
-    int ms_next_flip;    // site is kept / flips
+    int d_next_keep;     // d = 2 - m of the site after the next one, if the next
+    int d_next_flip;     // site is kept / flips
 };
 
 // Fills the records: five thresholds S = T - 1 (by m) from table[k*5 + m], a
@@ -197,10 +201,10 @@ __device__ __forceinline__ void chain_prime(ChainState<L>& st, const R& recs)
         for (int w = 0; w < RowWords<L>::WPR; ++w)
             nb[w] = row_bonds<L>(st.rb.cur, w);
         st.rb.R0next = site_word0<L>(nb, st.rb.cur[0], st.rb.up[0], st.rb.dn[0]);
-        st.ms = word_ms<0>(st.rb.R0next, false);
-        st.ms_next_keep = word_ms<1>(st.rb.R0next, false);
-        st.ms_next_flip = word_ms<1>(st.rb.R0next, true);
-        st.thr_keep = recs.thr(st.z, st.ms);
+        st.d = word_d<0>(st.rb.R0next, false);
+        st.d_next_keep = word_d<1>(st.rb.R0next, false);
+        st.d_next_flip = word_d<1>(st.rb.R0next, true);
+        st.thr_keep = recs.thr(st.z, st.d);
         st.thr_flip = st.thr_keep;
         st.prev_flip = false;
     }
@@ -214,10 +218,10 @@ __device__ __forceinline__ void chain_row_begin(ChainState<L>& st, const R& recs
         rowwords_begin<L>(st.rb, false);
     } else {
         rowwords_begin<L>(st.rb);
-        st.ms = site_ms<L, 0>(st.rb, false);
-        st.ms_next_keep = site_ms<L, 1>(st.rb, false);
-        st.ms_next_flip = site_ms<L, 1>(st.rb, true);
-        st.thr_keep = recs.thr(st.z, st.ms);
+        st.d = site_d<L, 0>(st.rb, false);
+        st.d_next_keep = site_d<L, 1>(st.rb, false);
+        st.d_next_flip = site_d<L, 1>(st.rb, true);
+        st.thr_keep = recs.thr(st.z, st.d);
         st.thr_flip = st.thr_keep;
         st.prev_flip = false;
     }
@@ -247,14 +251,14 @@ __device__ __forceinline__ void chain_attempt(ChainState<L>& st, Words4& rc, Wor
     if constexpr ((P >> 2) + 1 < BLOCKS)
         draws.template advance<(P >> 2) + 1, (P & 3)>(rn);
     const uint32_t r = rc.w[P & 3];
-    const uint32_t zf = st.z - (uint32_t)(st.ms * (int)R::STRIDE);
-    const int ms_keep = st.ms_next_keep, ms_flip = st.ms_next_flip;
+    const uint32_t zf = R::target(st.z, st.d);
+    const int d_keep = st.d_next_keep, d_flip = st.d_next_flip;
     uint32_t next_keep = 0u, next_flip = 0u;
     constexpr bool SEAM = Seamless<L>::value;
     // the next site: X+1 of this row, or (seamless rows) site 0 of the next
     if constexpr (X + 1 < L || SEAM) {
-        next_keep = recs.thr(st.z, ms_keep);
-        next_flip = recs.thr(zf, ms_flip);
+        next_keep = recs.thr(st.z, d_keep);
+        next_flip = recs.thr(zf, d_flip);
     }
     recs.count(st.z, X == 0 ? st.inc_last : inc);
     __builtin_amdgcn_sched_barrier(0);
@@ -267,14 +271,14 @@ __device__ __forceinline__ void chain_attempt(ChainState<L>& st, Words4& rc, Wor
     if constexpr (SEAM && X + 3 == L)
         rowwords_prepare_next<L>(st.rb);
     if constexpr (X + 2 < L) {
-        st.ms_next_keep = site_ms<L, X + 2>(st.rb, false);
-        st.ms_next_flip = site_ms<L, X + 2>(st.rb, true);
+        st.d_next_keep = site_d<L, X + 2>(st.rb, false);
+        st.d_next_flip = site_d<L, X + 2>(st.rb, true);
     } else if constexpr (SEAM && X + 2 == L) {
-        st.ms_next_keep = word_ms<0>(st.rb.R0next, false);
-        st.ms_next_flip = st.ms_next_keep;
+        st.d_next_keep = word_d<0>(st.rb.R0next, false);
+        st.d_next_flip = st.d_next_keep;
     } else if constexpr (SEAM && X + 1 == L) {
-        st.ms_next_keep = word_ms<1>(st.rb.R0next, false);
-        st.ms_next_flip = word_ms<1>(st.rb.R0next, true);
+        st.d_next_keep = word_d<1>(st.rb.R0next, false);
+        st.d_next_flip = word_d<1>(st.rb.R0next, true);
     }
     __builtin_amdgcn_sched_barrier(0);
     st.z = accept ? zf : st.z;
@@ -284,7 +288,7 @@ __device__ __forceinline__ void chain_attempt(ChainState<L>& st, Words4& rc, Wor
     if constexpr (X + 1 == L)
         st.inc_last = inc;
     if constexpr (X + 1 < L || SEAM) {
-        st.ms = accept ? ms_flip : ms_keep;
+        st.d = accept ? d_flip : d_keep;
         st.thr_keep = next_keep;
         st.thr_flip = next_flip;
         st.prev_flip = accept;

@@ -58,12 +58,12 @@ bool fast_table(uint32_t N, const uint64_t* t5, uint32_t* f, uint32_t stride)
             const long kp = (long)k + 2 - m;
             const uint64_t t = t5[(size_t)k * 5 + (4 - m)];
             if (kp < 0 || kp > (long)N || k == 1 || k == N - 1 || kp == 1 || kp == (long)N - 1) {
-                f[(size_t)k * stride + m] = 0u;
+                f[(size_t)k * stride + (4 - m)] = 0u;
                 continue;
             }
             if (t == 0)
                 return false;
-            f[(size_t)k * stride + m] = (uint32_t)(t - 1);
+            f[(size_t)k * stride + (4 - m)] = (uint32_t)(t - 1);
         }
     }
     return true;

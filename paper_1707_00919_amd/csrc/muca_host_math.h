@@ -15,9 +15,10 @@ namespace muca_host {
 void compute_thresholds(uint32_t N, const double* om, uint64_t* t5);
 // Generic-kernel table: uint64 thresholds of the four energy-changing moves.
 void device_table(uint32_t N, const uint64_t* t5, uint64_t* t4);
-// Table of the fast, split and wide kernels: uint32 S = T - 1 at f[k*stride + m]
-// by the number m of anti-aligned neighbours (stride 5, or 8 for the wide
-// kernel's 32-byte records, the rest zero); false if a move that can be
+// Table of the fast, split and wide kernels: uint32 S = T - 1 at
+// f[k*stride + 4 - m] by the number m of anti-aligned neighbours, i.e. at
+// slot 2 + d for the bin change d = 2 - m of the move (stride 5, or 8 for the
+// wide kernel's 32-byte records, the rest zero); false if a move that can be
 // proposed has T = 0.
 bool fast_table(uint32_t N, const uint64_t* t5, uint32_t* f, uint32_t stride);
 double flatness_of(uint32_t N, const uint64_t* H);

@@ -247,7 +247,7 @@ __global__ __launch_bounds__(64) void sweep_range_kernel(RangeArgs a)
         const uint32_t r = philox10(i >> 2, c1, c2, 0u, a.seed, w).w[i & 3u];
         bool accept;
         if constexpr (kFast) {
-            accept = r <= static_cast<const uint32_t*>(a.table)[k * (int)a.table_stride + (int)m];
+            accept = r <= static_cast<const uint32_t*>(a.table)[k * (int)a.table_stride + 4 - (int)m];
         } else {
             const uint32_t slot = m - (m > 2u ? 1u : 0u);
             accept = (m == 2u) || ((uint64_t)r < static_cast<const uint64_t*>(a.table)[k * 4 + (int)slot]);

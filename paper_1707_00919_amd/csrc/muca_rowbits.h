@@ -11,9 +11,10 @@
 //   bits 16..23  site differs from the site above, for sites 8i..8i+7,
 //   bits 24..31  site differs from the site below.
 // The number m of neighbours anti-aligned with site x = 8i + j is then the
-// popcount of bits j, j+1, 16+j, 24+j of R[i], and m - 2 is minus the change
-// of the energy bin if site x flips (Delta E = 8 - 4m for the 2D Ising model,
-// Sec. 3).  Flipping site x toggles bond x, the left bond of site x+1 (bit
+// popcount of bits j, j+1, 16+j, 24+j of R[i]; the chain carries d = 2 - m,
+// the change of the energy bin if site x flips (Delta E = 8 - 4m for the 2D
+// Ising model, Sec. 3), which is the popcount of the same bits of ~R[i],
+// minus 2.  Flipping site x toggles bond x, the left bond of site x+1 (bit
 // j+1 of its word); the last site's right bond is bond L-1, toggled when site
 // 0 flips.  The row's flips are collected as words (bit x: site x flipped)
 // and applied at the row end.
@@ -104,22 +105,22 @@ __device__ __forceinline__ void rowwords_prepare_next(RowWords<L>& rb)
     rb.R0next = site_word0<L>(nb, rb.dn[0], rb.cur[0] ^ rb.flips[0], rb.nx[0]);
 }
 
-// m - 2 of site 8i + J from its site word (m: anti-aligned neighbours), with
-// its left bond toggled when flipped_left.
+// d = 2 - m of site 8i + J from its site word (m: anti-aligned neighbours),
+// with its left bond toggled when flipped_left.
 template <int J>
-__device__ __forceinline__ int word_ms(uint32_t word, bool flipped_left)
+__device__ __forceinline__ int word_d(uint32_t word, bool flipped_left)
 {
     constexpr uint32_t MASK = (1u << J) | (1u << (J + 1)) | (1u << (16 + J)) | (1u << (24 + J));
     const uint32_t w = flipped_left ? (word ^ (1u << J)) : word;
-    return (int)__builtin_popcount(w & MASK) - 2;
+    return (int)__builtin_popcount(~w & MASK) - 2;
 }
 
-// m - 2 of site X, with its left bond toggled when flipped_left (site X-1
+// d = 2 - m of site X, with its left bond toggled when flipped_left (site X-1
 // flipped in this row).
 template <int L, int X>
-__device__ __forceinline__ int site_ms(const RowWords<L>& rb, bool flipped_left)
+__device__ __forceinline__ int site_d(const RowWords<L>& rb, bool flipped_left)
 {
-    return word_ms<X & 7>(rb.R[X >> 3], flipped_left);
+    return word_d<X & 7>(rb.R[X >> 3], flipped_left);
 }
 
 // After the first site of the row: if it flipped, so did bond L-1, the last

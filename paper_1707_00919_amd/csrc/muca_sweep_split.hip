@@ -124,7 +124,7 @@ __device__ __forceinline__ void sweep_split_kernel_body(const FastSweepArgs& a, 
     const uint32_t live = w < a.walkers ? 1u : 0u;
     R recs;
     if constexpr (WIDE)
-        recs = GlobalRecords{reinterpret_cast<const uint8_t*>(a.table), lds};
+        recs = GlobalRecords{reinterpret_cast<const uint8_t*>(a.table) + 8, lds};
     else
         recs = LdsRecords{lds};
     if (consumer) {

@@ -36,7 +36,7 @@ __device__ __forceinline__ void sweep_wide_kernel_body(const FastSweepArgs& a, u
 
     uint32_t* const mine = a.spins + w;
     const size_t stride = a.wpad;
-    const GlobalRecords recs{reinterpret_cast<const uint8_t*>(a.table), reinterpret_cast<uint8_t*>(counters)};
+    const GlobalRecords recs{reinterpret_cast<const uint8_t*>(a.table) + 8, reinterpret_cast<uint8_t*>(counters)};
     ChainState<L> st;
     chain_load<L, GlobalRecords>(st, mine, stride, a.energy[w]);
     chain_prime<L>(st, recs);

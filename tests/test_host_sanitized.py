@@ -316,7 +316,8 @@ def test_host_math_under_sanitizers_matches_oracle(driver, L, seed, kind):
     ok = bool(np.all(t_by_m[proposable] > 0))
     assert bool(out["ok5"]) == ok and bool(out["ok8"]) == ok
     if ok:
-        want = np.where(proposable, t_by_m - 1, 0).astype(np.uint32)
+        # slot 4 - m (= 2 + d for the bin change d = 2 - m of the move)
+        want = np.where(proposable, t_by_m - 1, 0).astype(np.uint32)[:, ::-1]
         np.testing.assert_array_equal(out["f5"].reshape(N + 1, 5), want)
         f8 = out["f8"].reshape(N + 1, 8)
         np.testing.assert_array_equal(f8[:, :5], want)
