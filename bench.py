@@ -55,7 +55,7 @@ ALU_OPS_PER_ATTEMPT = 5 + 10 + 13
 # gather (4 B) and the histogram counter's read-modify-write (4 + 4 B) -- plus
 # the random words handed over through LDS in the two-wave form (4 B written,
 # 4 B read).  Peak: 128 B per clock per CU.
-LDS_BYTES_PER_ATTEMPT = {2: 4 + 8 + 8, 1: 4 + 8, 0: 8 + 8, 3: 8, 4: 8 + 8}
+LDS_BYTES_PER_ATTEMPT = {2: 4 + 8 + 8, 5: 4 + 8 + 8, 1: 4 + 8, 0: 8 + 8, 3: 8, 4: 8 + 8}
 
 
 def lds_bytes_per_attempt(variant, L):
@@ -86,7 +86,7 @@ def exact_ln_g(L):
 
 
 KERNEL_NAMES = {0: "sweep_kernel", 1: "sweep_fast_kernel", 2: "sweep_split_kernel", 3: "sweep_wide_kernel",
-                4: "sweep_wide_split_kernel"}
+                4: "sweep_wide_split_kernel", 5: "sweep_pair_kernel"}
 
 
 def solve(Solver, wl, seed, iter_cap):

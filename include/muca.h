@@ -118,8 +118,9 @@ typedef struct muca_info {
     double kernel_ms;       /* device time of the sweep launches (HIP events) */
     uint32_t kernel_launches; /* sweep kernel launches of the call           */
     uint32_t kernel_variant;  /* 0: generic, 1: fast, 2: split, 3: wide,
-                                 4: wide two-wave sweep kernel (the last of
-                                 the call)                                   */
+                                 4: wide two-wave, 5: two-wave pairs (two
+                                 chains sharing one table) sweep kernel (the
+                                 last of the call)                           */
     uint32_t width;           /* bins from the lowest to the highest visited
                                  bin of H, inclusive (full range: N + 1)     */
     uint32_t reserved;

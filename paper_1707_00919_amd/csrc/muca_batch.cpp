@@ -40,7 +40,7 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 thread_local std::string g_batch_error;
 
 // kernel forms, as in muca_info::kernel_variant
-constexpr uint32_t kGeneric = 0, kFast = 1, kSplit = 2, kWide = 3, kWideSplit = 4;
+constexpr uint32_t kGeneric = 0, kFast = 1, kSplit = 2, kWide = 3, kWideSplit = 4, kPair = 5;
 
 struct Group {
     uint32_t L = 0;
@@ -211,6 +211,8 @@ int enqueue_round(muca_batch* b, size_t stage_used, const std::vector<Group>& gr
         hipError_t e;
         if (G.form == kSplit)
             e = muca::launch_split_batch(G.L, fargs, items + G.first_item, G.nitems, s);
+        else if (G.form == kPair)
+            e = muca::launch_pair_batch(G.L, fargs, items + G.first_item, G.nitems, s);
         else if (G.form == kWideSplit)
             e = muca::launch_wide_split_batch(G.L, fargs, items + G.first_item, G.nitems, s);
         else if (G.form == kWide)
@@ -494,25 +496,43 @@ static int muca_batch_submit_impl(muca_batch* b, const uint32_t* mode, const uin
         return MUCA_OK;
     }
     // two-wave form while all of the batch's two-wave workgroups fit on the
-    // device at once, at most two per CU (LDS shares weighted by each L)
-    std::vector<double> share(count, 0.0);
-    double lds_share = 0.0;
+    // device at once, at most two chains per CU (LDS shares weighted by each
+    // L): with one workgroup each, or else with the pair form (two chains
+    // sharing one table) for the members whose workgroup fills a CU
+    std::vector<double> share(count, 0.0), share_pair(count, 0.0);
+    std::vector<char> pairable(count, 0);
+    double lds_share = 0.0, lds_share_pair = 0.0;
     uint64_t walkers = 0;
     for (uint32_t i = 0; i < count; ++i) {
         if (mode[i] == MUCA_BATCH_SKIP)
             continue;
         walkers += b->m[i]->p.walkers;
         const uint32_t L = b->m[i]->L;
+        const double nb = (double)(b->m[i]->wpad / muca::kWave);
         uint32_t bytes = 0;
         if (form[i] == kFast && muca::split_sweep_supported(L))
             bytes = muca::split_lds_bytes(L);
         else if (form[i] == kWide && muca::wide_split_supported(L))
             bytes = muca::wide_split_lds_bytes(L);
         if (bytes)
-            share[i] = (double)(b->m[i]->wpad / muca::kWave) * std::max(0.5, 1.0 / (double)(muca::kLdsPerCu / bytes));
+            share[i] = nb * std::max(0.5, 1.0 / (double)(muca::kLdsPerCu / bytes));
+        share_pair[i] = share[i];
+        if (form[i] == kFast && muca::pair_sweep_supported(L) &&
+            muca::split_groups_per_cu(muca::split_lds_bytes(L)) == 1u &&
+            !(b->m[i]->p.flags & MUCA_FLAG_FAST_KERNEL)) {
+            pairable[i] = 1;
+            share_pair[i] = 0.5 * nb;
+        }
         lds_share += share[i];
+        lds_share_pair += share_pair[i];
     }
-    const bool two_wave = active_blocks <= 2u * (uint32_t)b->cus && lds_share <= (double)b->cus;
+    const bool fits_blocks = active_blocks <= 2u * (uint32_t)b->cus;
+    const bool two_wave_single = fits_blocks && lds_share <= (double)b->cus;
+    const bool two_wave = two_wave_single || (fits_blocks && lds_share_pair <= (double)b->cus);
+    // pairs wherever a round does not fit with one workgroup per chain
+    const bool use_pairs = !two_wave_single;
+    if (use_pairs)
+        share = share_pair;
     b->tuning = false;
     b->round_walkers = walkers;
     if (two_wave) {
@@ -529,10 +549,12 @@ static int muca_batch_submit_impl(muca_batch* b, const uint32_t* mode, const uin
     }
     // the kernel form of the choice (the merge-cadence choice keeps the default shape)
     const int shape = b->choice == kTwoMerges ? (two_wave ? kTwoWave : kMixed) : b->choice;
-    // members in the two-wave form: all, or (mixed) those with the fewest
-    // walkers while their workgroups fit -- a population with fewer walkers
-    // needs more weight iterations, so its chains are the ones later rounds
-    // wait for, and it costs the least room
+    // members in the two-wave form: all, or (mixed) as many as fit, those
+    // with the longest chains first -- a round lasts as long as its longest
+    // chain (sites x sweeps of one walker), which the two-wave form shortens
+    // most -- and among equal chains those with the fewest walkers: a
+    // population with fewer walkers needs more weight iterations, so its
+    // chains are the ones later rounds wait for, and it costs the least room
     std::vector<char> two(count, 0);
     if (shape == kTwoWave) {
         std::fill(two.begin(), two.end(), 1);
@@ -541,8 +563,10 @@ static int muca_batch_submit_impl(muca_batch* b, const uint32_t* mode, const uin
         for (uint32_t i = 0; i < count; ++i)
             if (mode[i] != MUCA_BATCH_SKIP && share[i] > 0.0)
                 order.push_back(i);
-        std::stable_sort(order.begin(), order.end(),
-                         [&](uint32_t x, uint32_t y) { return b->m[x]->p.walkers < b->m[y]->p.walkers; });
+        std::stable_sort(order.begin(), order.end(), [&](uint32_t x, uint32_t y) {
+            const uint64_t cx = (uint64_t)b->m[x]->N * total[x], cy = (uint64_t)b->m[y]->N * total[y];
+            return cx != cy ? cx > cy : b->m[x]->p.walkers < b->m[y]->p.walkers;
+        });
         double used = 0.0;
         size_t blocks = 0;
         for (uint32_t i : order) {
@@ -562,7 +586,10 @@ static int muca_batch_submit_impl(muca_batch* b, const uint32_t* mode, const uin
             form[i] = kWideSplit;  // the same tables, Philox on a second wave
         if (form[i] == kFast) {
             const bool want_fast = (b->m[i]->p.flags & MUCA_FLAG_FAST_KERNEL) != 0 || !two[i];
-            if (muca::split_sweep_supported(L) && !(want_fast && muca::fast_sweep_supported(L))) {
+            if (two[i] && use_pairs && pairable[i]) {
+                form[i] = kPair;
+                waves[i] = 2u;  // two chains count into one table
+            } else if (muca::split_sweep_supported(L) && !(want_fast && muca::fast_sweep_supported(L))) {
                 form[i] = kSplit;
             } else {
                 form[i] = kFast;
@@ -594,10 +621,11 @@ static int muca_batch_submit_impl(muca_batch* b, const uint32_t* mode, const uin
         G.waves = waves[mem.front()];
         G.first_item = nitems;
         for (uint32_t i : mem) {
-            // a work item is one workgroup: 64 walkers, or for the one-wave form
-            // fast_waves_per_group(L) blocks of 64 that share one table
+            // a work item is one workgroup: 64 walkers, or for the one-wave
+            // form fast_waves_per_group(L) blocks of 64 (for the pair form two)
+            // that share one table
             const uint32_t blocks = b->m[i]->wpad / muca::kWave;
-            const uint32_t per = G.form == kFast ? G.waves : 1u;
+            const uint32_t per = (G.form == kFast || G.form == kPair) ? G.waves : 1u;
             for (uint32_t blk = 0; blk < (blocks + per - 1) / per; ++blk)
                 items[nitems++] = muca::BatchItem{i, blk};
             key += std::to_string(i) + ":" + std::to_string(total[i]) + ",";

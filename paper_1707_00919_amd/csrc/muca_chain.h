@@ -227,7 +227,7 @@ __device__ __forceinline__ void chain_row_begin(ChainState<L>& st, const R& recs
     }
 }
 
-// Attempt at site X = P % L; P counts the sites of the loop step.
+// Attempt at site X of the row; P counts the sites of the loop step.
 //
 // Order inside one attempt: first the two threshold loads that site X+1 may
 // need (they depend only on the state after site X-1: its left bond, to site
@@ -241,11 +241,10 @@ __device__ __forceinline__ void chain_row_begin(ChainState<L>& st, const R& recs
 // behind), and the counts between the compare and the selects.  For the last
 // site, the right bond (to site 0) already carries site 0's flip
 // (rowwords_note_first).
-template <int L, int P, int BLOCKS, class R, class Draws>
+template <int L, int X, int P, int BLOCKS, class R, class Draws>
 __device__ __forceinline__ void chain_attempt(ChainState<L>& st, Words4& rc, Words4& rn, Draws& draws,
                                               const R& recs, uint32_t inc)
 {
-    constexpr int X = P % L;
     if constexpr ((P & 3) == 0)
         rc = rn;
     if constexpr ((P >> 2) + 1 < BLOCKS)
@@ -295,28 +294,31 @@ __device__ __forceinline__ void chain_attempt(ChainState<L>& st, Words4& rc, Wor
     }
 }
 
-template <int L, int RR, int BLOCKS, class R, class Draws, int... Xs>
+template <int L, int X0, int P0, int BLOCKS, class R, class Draws, int... Xs>
 __device__ __forceinline__ void chain_row_sites(ChainState<L>& st, Words4& rc, Words4& rn, Draws& draws,
                                                 const R& recs, uint32_t inc, std::integer_sequence<int, Xs...>)
 {
-    (chain_attempt<L, RR * L + Xs, BLOCKS>(st, rc, rn, draws, recs, inc), ...);
+    (chain_attempt<L, X0 + Xs, P0 + Xs, BLOCKS>(st, rc, rn, draws, recs, inc), ...);
 }
 
-// Row RR of a loop step of BLOCKS Philox blocks that starts at row y: prefetch
-// row y+RR+2, run the row's L attempts, write the row back and slide the
-// window down by one.
-template <int L, int RR, int BLOCKS, class R, class Draws>
-__device__ __forceinline__ void chain_row(ChainState<L>& st, Words4& rc, Words4& rn, Draws& draws,
-                                          const R& recs, uint32_t inc, uint32_t* mine, size_t stride, int y)
+// Row yy's start: prefetch row yy+2 and form the row's site words.
+template <int L, class R>
+__device__ __forceinline__ void chain_row_open(ChainState<L>& st, const R& recs, const uint32_t* mine, size_t stride,
+                                               uint32_t yy)
 {
     constexpr int WPR = ChainShape<L>::WPR;
-    const uint32_t yy = (uint32_t)(y + RR);
     const uint32_t ynext = yy + 2u < (uint32_t)L ? yy + 2u : yy + 2u - (uint32_t)L;
 #pragma unroll
     for (int j = 0; j < WPR; ++j)
         st.rb.nx[j] = mine[(size_t)(ynext * WPR + j) * stride];
     chain_row_begin<L>(st, recs);
-    chain_row_sites<L, RR, BLOCKS>(st, rc, rn, draws, recs, inc, std::make_integer_sequence<int, L>{});
+}
+
+// Row yy's end: write the row back and slide the window down by one.
+template <int L>
+__device__ __forceinline__ void chain_row_close(ChainState<L>& st, uint32_t* mine, size_t stride, uint32_t yy)
+{
+    constexpr int WPR = ChainShape<L>::WPR;
     rowwords_end<L>(st.rb);
 #pragma unroll
     for (int j = 0; j < WPR; ++j) {
@@ -325,6 +327,18 @@ __device__ __forceinline__ void chain_row(ChainState<L>& st, Words4& rc, Words4&
         st.rb.cur[j] = st.rb.dn[j];
         st.rb.dn[j] = st.rb.nx[j];
     }
+}
+
+// Row RR of a loop step of BLOCKS Philox blocks that starts at row y: its L
+// attempts between the row's start and end.
+template <int L, int RR, int BLOCKS, class R, class Draws>
+__device__ __forceinline__ void chain_row(ChainState<L>& st, Words4& rc, Words4& rn, Draws& draws,
+                                          const R& recs, uint32_t inc, uint32_t* mine, size_t stride, int y)
+{
+    const uint32_t yy = (uint32_t)(y + RR);
+    chain_row_open<L>(st, recs, mine, stride, yy);
+    chain_row_sites<L, 0, RR * L, BLOCKS>(st, rc, rn, draws, recs, inc, std::make_integer_sequence<int, L>{});
+    chain_row_close<L>(st, mine, stride, yy);
 }
 
 template <int L, int RPS, class R, class Draws, int... RRs>
@@ -343,6 +357,17 @@ __device__ __forceinline__ void chain_rows(ChainState<L>& st, Words4& rc, Words4
 {
     static_assert((RPS * L) % 4 == 0, "a loop step is whole Philox blocks");
     chain_rows_seq<L, RPS>(st, rc, rn, draws, recs, inc, mine, stride, y, std::make_integer_sequence<int, RPS>{});
+}
+
+// Sites X0 .. X0+NX-1 of the current row as one loop step of whole Philox
+// blocks (a part of a row between chain_row_open and chain_row_close); rn
+// holds the step's first block.
+template <int L, int X0, int NX, class R, class Draws>
+__device__ __forceinline__ void chain_row_part(ChainState<L>& st, Words4& rc, Words4& rn, Draws& draws,
+                                               const R& recs, uint32_t inc)
+{
+    static_assert(X0 % 4 == 0 && NX % 4 == 0 && X0 + NX <= L, "a loop step is whole Philox blocks of one row");
+    chain_row_sites<L, X0, 0, NX / 4>(st, rc, rn, draws, recs, inc, std::make_integer_sequence<int, NX>{});
 }
 
 }  // namespace muca

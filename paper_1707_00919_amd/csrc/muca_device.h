@@ -39,7 +39,7 @@ struct SweepArgs {
 
 // Arguments of the fast and split sweeps (L <= 64): table holds, for every bin k and
 // every count m = 0..4 of anti-aligned neighbours, S = T - 1 of the move with
-// energy change 8 - 4m at table[k*5 + m] (valid when no reachable T is 0).
+// energy change 8 - 4m at table[k*5 + 4 - m] (valid when no reachable T is 0).
 struct FastSweepArgs {
     uint32_t* spins;
     int32_t* energy;
@@ -60,6 +60,33 @@ struct BatchItem {
     uint32_t member;
     uint32_t block;
 };
+
+// A batch member's arguments as a kernel's own.  They are read through the
+// constant address space (the table of arguments does not change while the
+// kernel runs): a pointer loaded from there is taken to point to global
+// memory, where one read from generic memory would stay generic -- and
+// generic (flat) accesses share the counter that tracks LDS loads, so that
+// every wait for an LDS result would drain all of them -- and no store of the
+// sweep can be taken to change the arguments.
+template <class A>
+__device__ __forceinline__ A member_args(const A* args, uint32_t member)
+{
+    using CA = const __attribute__((address_space(4))) A;
+    const CA* c = (const CA*)args + member;
+    A a;
+    a.spins = c->spins;
+    a.energy = c->energy;
+    a.table = c->table;
+    a.hist = c->hist;
+    a.sweep0 = c->sweep0;
+    a.wpad = c->wpad;
+    a.walkers = c->walkers;
+    a.seed = c->seed;
+    a.nsweeps = c->nsweeps;
+    a.therm = c->therm;
+    a.pad = 0u;
+    return a;
+}
 
 struct InitArgs {
     uint32_t* spins;
@@ -113,6 +140,24 @@ __host__ __device__ constexpr uint32_t split_rows_per_step(uint32_t L, bool wide
     return rows;
 }
 
+// The pair form of the two-wave sweep: two chain waves of 64 walkers share one
+// record table, each with a producer wave and a ring of its own, so that a CU
+// whose LDS holds one table runs two chains.  A loop step is a row, or half a
+// row where two rings of two row-long slots would not fit beside the table
+// (L = 64); 0 where neither fits or a half row is not whole Philox blocks.
+__host__ __device__ constexpr uint32_t pair_lds_bytes_for(uint32_t L, uint32_t sites)
+{
+    return (28u * (L * L + 1u) + 15u) / 16u * 16u + 2u * 2u * (sites / 4u) * (uint32_t)kWave * 16u;
+}
+__host__ __device__ constexpr uint32_t pair_sites_per_step(uint32_t L)
+{
+    return L % 4u != 0u || L > 64u ? 0u
+           : pair_lds_bytes_for(L, L) <= kLdsPerCu ? L
+           : (L % 8u == 0u && pair_lds_bytes_for(L, L / 2u) <= kLdsPerCu) ? L / 2u
+                                                                          : 0u;
+}
+__host__ __device__ constexpr uint32_t pair_lds_bytes(uint32_t L) { return pair_lds_bytes_for(L, pair_sites_per_step(L)); }
+
 // LDS bytes of one workgroup of the split sweep (L <= 64) and of the wide
 // two-wave sweep (L > 64).
 __host__ __device__ constexpr uint32_t split_lds_bytes(uint32_t L)
@@ -149,6 +194,15 @@ inline bool prefer_wide_split(uint32_t L, uint64_t blocks, uint32_t cus)
 {
     return prefer_two_waves(wide_split_lds_bytes(L), blocks, cus);
 }
+// Where one two-wave workgroup per CU is all that fits and there are more
+// 64-walker blocks than CUs, the pair form runs two chains per CU: it pays
+// while all of its workgroups are resident at once.
+bool pair_sweep_supported(uint32_t L);
+inline bool prefer_pair(uint32_t L, uint64_t blocks, uint32_t cus)
+{
+    return pair_sweep_supported(L) && split_groups_per_cu(split_lds_bytes(L)) == 1u && blocks > cus &&
+           (blocks + 1u) / 2u <= (uint64_t)cus * split_groups_per_cu(pair_lds_bytes(L));
+}
 
 // Largest number of recorded sweeps one launch may run without a 32-bit LDS
 // histogram counter overflowing: every walker of a workgroup (64 per wave,
@@ -167,9 +221,11 @@ bool fast_sweep_supported(uint32_t L);
 hipError_t launch_fast_sweep(uint32_t L, const FastSweepArgs& a, hipStream_t s);
 bool split_sweep_supported(uint32_t L);
 hipError_t launch_split_sweep(uint32_t L, const FastSweepArgs& a, hipStream_t s);
+// The pair form: one workgroup of four waves per two 64-walker blocks.
+hipError_t launch_pair_sweep(uint32_t L, const FastSweepArgs& a, hipStream_t s);
 hipError_t launch_init(const InitArgs& a, hipStream_t s);
 // L > 64 with the thresholds in global memory: table holds, per bin k, S =
-// T - 1 of the move with m anti-aligned neighbours at table[k*8 + m]
+// T - 1 of the move with m anti-aligned neighbours at table[k*8 + 4 - m]
 // (32-byte records; valid when no reachable T is 0).
 bool wide_sweep_supported(uint32_t L);
 hipError_t launch_wide_sweep(uint32_t L, const FastSweepArgs& a, hipStream_t s);
@@ -182,7 +238,7 @@ hipError_t launch_fill_u64(unsigned long long* p, size_t n, hipStream_t s);
 // Arguments of a partial sweep: sites [site_begin, site_end) of one sweep, in
 // typewriter order, the sites from rec_begin on counted in the histogram.
 // table is in the generic layout (uint64, 4 per bin; table_stride 0) or holds
-// uint32 S = T - 1 by m, table_stride words per bin (5, or 8 for L > 64).
+// uint32 S = T - 1 by 4 - m, table_stride words per bin (5, or 8 for L > 64).
 struct RangeArgs {
     uint32_t* spins;
     int32_t* energy;
@@ -203,6 +259,9 @@ hipError_t launch_sweep_batch(uint32_t L, const SweepArgs* args, const BatchItem
 hipError_t launch_fast_batch(uint32_t L, uint32_t G, const FastSweepArgs* args, const BatchItem* items,
                              uint32_t nitems, hipStream_t s);
 hipError_t launch_wide_batch(uint32_t L, const FastSweepArgs* args, const BatchItem* items, uint32_t nitems,
+                             hipStream_t s);
+// Pair-form work items: BatchItem::block is the pair's index (blocks 2i, 2i+1).
+hipError_t launch_pair_batch(uint32_t L, const FastSweepArgs* args, const BatchItem* items, uint32_t nitems,
                              hipStream_t s);
 hipError_t launch_split_batch(uint32_t L, const FastSweepArgs* args, const BatchItem* items,
                               uint32_t nitems, hipStream_t s);

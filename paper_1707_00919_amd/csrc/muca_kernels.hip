@@ -278,7 +278,7 @@ template <int L>
 __global__ __launch_bounds__(64) void sweep_kernel_batch(const SweepArgs* args, const BatchItem* items)
 {
     const BatchItem it = items[blockIdx.x];
-    sweep_kernel_body<L>(args[it.member], it.block);
+    sweep_kernel_body<L>(member_args(args, it.member), it.block);
 }
 
 template <int L>

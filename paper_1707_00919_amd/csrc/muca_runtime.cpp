@@ -217,8 +217,8 @@ hipError_t enqueue_call(const CallTarget& t, const uint64_t* table5, const Segme
 {
     const uint32_t N = t.L * t.L;
     const size_t table_bytes = (size_t)(N + 1) * 4 * sizeof(uint64_t);
-    // kernel choice: 4 wide two-wave, 3 wide, 2 split, 1 fast, 0 generic (all
-    // give the same bits)
+    // kernel choice: 5 two-wave pairs, 4 wide two-wave, 3 wide, 2 split,
+    // 1 fast, 0 generic (all give the same bits)
     uint32_t variant = 0;
     if (!(t.flags & MUCA_FLAG_GENERIC_KERNEL) && muca::wide_sweep_supported(t.L) &&
         fast_table(N, table5, reinterpret_cast<uint32_t*>(t.h_table4), 8)) {
@@ -233,10 +233,16 @@ hipError_t enqueue_call(const CallTarget& t, const uint64_t* table5, const Segme
         // The split kernel gives each 64 walkers a second wave for the random
         // numbers; once its workgroups no longer all fit at once, or more than
         // two share a CU, the one-wave form wins.
-        const bool want_fast = (t.flags & MUCA_FLAG_FAST_KERNEL) != 0 ||
-                               (!muca::prefer_split(t.L, t.wpad / muca::kWave, (uint32_t)t.cus) &&
-                                muca::fast_sweep_supported(t.L));
-        if (muca::split_sweep_supported(t.L) && !(want_fast && muca::fast_sweep_supported(t.L)))
+        // Where one two-wave workgroup fills a CU and the blocks outnumber
+        // the CUs, the pair form gives each CU two chains.
+        const uint64_t blocks = t.wpad / muca::kWave;
+        const bool forced_fast = (t.flags & MUCA_FLAG_FAST_KERNEL) != 0;
+        const bool pair = !forced_fast && muca::prefer_pair(t.L, blocks, (uint32_t)t.cus);
+        const bool want_fast = forced_fast || (!muca::prefer_split(t.L, blocks, (uint32_t)t.cus) &&
+                                               muca::fast_sweep_supported(t.L));
+        if (pair)
+            variant = 5;
+        else if (muca::split_sweep_supported(t.L) && !(want_fast && muca::fast_sweep_supported(t.L)))
             variant = 2;
         else
             variant = 1;
@@ -281,7 +287,7 @@ hipError_t enqueue_call(const CallTarget& t, const uint64_t* table5, const Segme
             a.site_begin = g.site_begin;
             a.site_end = g.site_end;
             a.rec_begin = g.rec_begin;
-            a.table_stride = variant >= 3 ? 8u : (fast ? 5u : 0u);
+            a.table_stride = (variant == 3 || variant == 4) ? 8u : (fast ? 5u : 0u);
             MUCA_ENQ(muca::launch_sweep_range(a, stream), "partial sweep launch");
             ++launches;
             continue;
@@ -301,7 +307,8 @@ hipError_t enqueue_call(const CallTarget& t, const uint64_t* table5, const Segme
                 a.seed = t.seed;
                 a.nsweeps = n;
                 a.therm = th;
-                MUCA_ENQ(variant == 4   ? muca::launch_wide_split_sweep(t.L, a, stream)
+                MUCA_ENQ(variant == 5   ? muca::launch_pair_sweep(t.L, a, stream)
+                         : variant == 4 ? muca::launch_wide_split_sweep(t.L, a, stream)
                          : variant == 3 ? muca::launch_wide_sweep(t.L, a, stream)
                          : variant == 2 ? muca::launch_split_sweep(t.L, a, stream)
                                         : muca::launch_fast_sweep(t.L, a, stream),

@@ -87,7 +87,7 @@ template <int L, int G>
 __global__ __launch_bounds__(64 * G) void sweep_fast_kernel_batch(const FastSweepArgs* args, const BatchItem* items)
 {
     const BatchItem it = items[blockIdx.x];
-    sweep_fast_kernel_body<L, G>(args[it.member], it.block);
+    sweep_fast_kernel_body<L, G>(member_args(args, it.member), it.block);
 }
 
 template <int L>

@@ -70,7 +70,7 @@ template <int L>
 __global__ __launch_bounds__(64) void sweep_wide_kernel_batch(const FastSweepArgs* args, const BatchItem* items)
 {
     const BatchItem it = items[blockIdx.x];
-    sweep_wide_kernel_body<L>(args[it.member], it.block);
+    sweep_wide_kernel_body<L>(member_args(args, it.member), it.block);
 }
 
 template <int L>

@@ -137,6 +137,31 @@ def test_kernel_variants_agree(L, W, seed):
         assert_state(s, o)
 
 
+@pytest.mark.parametrize("L,extra,trim,seed", [(48, 1, 0, 61), (52, 2, 5, 62), (56, 1, 63, 63), (64, 1, 0, 64),
+                                             (64, 2, 1, 65)])
+def test_pair_form_matches_oracle(L, extra, trim, seed):
+    # more 64-walker blocks than CUs where one two-wave workgroup fills a CU:
+    # the pair form (two chains sharing one table, whole-row steps at L = 48,
+    # 52, 56 and half-row steps at L = 64); an odd block count leaves the last
+    # pair's second chain idle; against the oracle and the one-wave form
+    import torch
+    from paper_1707_00919_amd import _abi
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    W = 64 * (cus + extra) - trim
+    note("pair form L=%d W=%d seed=%d" % (L, W, seed))
+    o = oracle.OracleMuca(L, W, seed)
+    om = smooth_log_weights(L, seed + 100)
+    o.set_log_weights(om)
+    oi = o.iterate(2, 3)
+    for flags, variant in [(0, 5), (_abi.MUCA_FLAG_FAST_KERNEL, 1)]:
+        s = Solver(L, W, seed, flags=flags)
+        s.set_log_weights(om)
+        si = s.iterate(2, 3)
+        assert si["kernel_variant"] == variant
+        assert_call(si, oi, s, o)
+        assert_state(s, o)
+
+
 @pytest.mark.parametrize("L,W,seed,default", [(80, 65, 31, 4), (96, 130, 32, 4), (112, 64, 33, 4),
                                               (128, 200, 34, 4), (96, 16448, 36, 3)])
 def test_wide_kernel_agrees(L, W, seed, default):
@@ -159,10 +184,13 @@ def test_wide_kernel_agrees(L, W, seed, default):
 
 
 def test_many_walkers_at_large_L_use_wave_groups():
-    # more two-wave workgroups than fit on the device at once: the one-wave
-    # form runs, with four waves sharing one record table at L = 64
-    note("wave groups L=64 W=16448")
-    L, W, seed = 64, 16448, 20
+    # more two-wave chains than fit on the device at once, even two per CU:
+    # the one-wave form runs, with four waves sharing one record table at
+    # L = 64
+    import torch
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    L, W, seed = 64, 64 * (2 * cus + 1), 20
+    note("wave groups L=%d W=%d" % (L, W))
     s = Solver(L, W, seed)
     o = oracle.OracleMuca(L, W, seed)
     om = smooth_log_weights(L, seed)
