@@ -147,6 +147,12 @@ def hardware_rate(Solver, wl, ln_g, warm_sweeps=20, timed_sweeps=200):
 KERNEL_SOURCES = ["muca_kernels.hip", "muca_sweep_fast.hip", "muca_sweep_split.hip", "muca_sweep_wide.hip",
                   "muca_chain.h", "muca_rowbits.h", "philox.h", "muca_device.h"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_sweep_L32_W16384.txt")
+# The chain wave's instruction count per attempt of the headline kernel (from
+# its gfx950 assembly, checked against SQ_INSTS_* counters), for the third
+# roof: one chain wave per 64 walkers issues at most one instruction every 4
+# clocks, so no launch of W walkers beats (W / 64) * 64 * 2.4e9 / (4 * count)
+# attempts/s while each chain wave has a SIMD to itself.
+CHAIN_FILE = os.path.join(ROOT, "profiles", "chain_issue_sweep_split_L32.md")
 COPY_BYTES = 256 << 20
 
 
@@ -184,6 +190,36 @@ def traffic_per_launch():
         "not measured in this run" % (rel, src))
 
 
+def summary_values(path):
+    """key = value lines of a committed profile summary."""
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            if "=" in line and not line.lstrip().startswith(("#", "|", "`")) and line.count("=") == 1:
+                k, v = line.split("=", 1)
+                vals[k.strip()] = v.strip()
+    return vals
+
+
+def chain_roof(attempts_per_s, walkers):
+    """The chain-issue roof of the headline kernel from the committed
+    instruction count (None and a note if the kernel sources changed since)."""
+    rel = os.path.relpath(CHAIN_FILE, ROOT)
+    src = kernel_source_hash()
+    if not os.path.exists(CHAIN_FILE):
+        return None, "no instruction count (%s missing)" % rel
+    vals = summary_values(CHAIN_FILE)
+    if vals.get("kernel_source_sha256_16") != src:
+        return None, "%s was taken on kernel sources %s, not the current %s: not used" % (
+            rel, vals.get("kernel_source_sha256_16"), src)
+    per = float(vals["chain_instructions_per_attempt"])
+    waves = -(-walkers // 64)
+    peak = min(waves, 256) * 64 * 2.4e9 / (4.0 * per)
+    return {"bound": "chain issue", "achieved": attempts_per_s, "peak": peak, "unit": "attempts/s",
+            "frac": attempts_per_s / peak, "chain_instructions_per_attempt": per, "chain_waves": waves,
+            "clocks_per_instruction": 4}, "instruction count from %s (kernel sources %s)" % (rel, src)
+
+
 def scaled_log_weights(L):
     """Near-flat log weights for a lattice with no exact table: the exact
     entropy of the L/2 lattice scaled to L (ln g_L(E) ~ 4 ln g_{L/2}(E/4),
@@ -197,24 +233,27 @@ def scaled_log_weights(L):
     return om - om.max()
 
 
-def profile_pass(Solver, wl, ln_g, sweeps=50):
+def profile_pass(Solver, wl, ln_g, sweeps=50, warm=0):
     """Short run for counter collection: one sweep launch of the benchmark
     shape at exact weights (near-flat scaled ones where no exact table
-    exists), then a plain device copy of COPY_BYTES bytes that calibrates
-    FETCH_SIZE / WRITE_SIZE."""
+    exists), after `warm` unrecorded sweeps that spread the walkers over the
+    energy range (their launches come first in a trace), then a plain device
+    copy of COPY_BYTES bytes that calibrates FETCH_SIZE / WRITE_SIZE."""
     import torch
     s = Solver(wl["L"], wl["walkers"], 12345)
     if ln_g is not None:
         s.set_log_weights(np.where(np.isfinite(ln_g), -ln_g, 0.0))
     else:
         s.set_log_weights(scaled_log_weights(wl["L"]))
+    if warm:
+        s.production(0, warm)
     info = s.production(0, sweeps)
     s.close()
     src = torch.ones(COPY_BYTES // 4, dtype=torch.int32, device="cuda")
     dst = torch.empty_like(src)
     dst.copy_(src)
     torch.cuda.synchronize()
-    print(json.dumps({"profile_pass": True, "attempts": info["attempts"],
+    print(json.dumps({"profile_pass": True, "warm_sweeps": warm, "width": info["width"], "attempts": info["attempts"],
                       "kernel_variant": info["kernel_variant"], "copy_bytes": COPY_BYTES,
                       "kernel_source_sha256_16": kernel_source_hash()}), flush=True)
 
@@ -708,6 +747,8 @@ def main():
     ap.add_argument("--issue-probe", action="store_true",
                     help="measure the issue rate of the sweep's integer instructions (the ALU roof)")
     ap.add_argument("--probe-iterations", type=int, default=16384)
+    ap.add_argument("--profile-warm", type=int, default=0,
+                    help="unrecorded sweeps before the profiled launch of --profile-pass")
     ap.add_argument("--profile-pass", action="store_true",
                     help="short sweep + calibration copy for rocprofv3 counter runs")
     args = ap.parse_args()
@@ -736,7 +777,7 @@ def main():
     wl = WORKLOADS[args.workload]
     ln_g = exact_ln_g(wl["L"])
     if args.profile_pass:
-        profile_pass(Solver, wl, ln_g)
+        profile_pass(Solver, wl, ln_g, warm=args.profile_warm)
         return
 
     for i in range(args.warmup):
@@ -822,6 +863,10 @@ def main():
             "ops_per_attempt": ALU_OPS_PER_ATTEMPT,
         },
     }
+    if args.workload == WORKLOAD:
+        roof, note = chain_roof(attempts / (kernel_ms * 1e-3), wl["walkers"])
+        out["roofline_chain"] = roof
+        out["roofline_chain_source"] = note
     lds_b = lds_bytes_per_attempt(main_variant, wl["L"])
     lds_rate = lds_b * attempts_per_launch / avg_launch_s
     out["roofline_lds"] = {"achieved": lds_rate / 1e12, "peak": LDS_PEAK_BYTES / 1e12, "unit": "TB/s",
