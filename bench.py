@@ -353,7 +353,8 @@ def batched_solve(Batch, Solver, inst, flags, iter_sweeps, min_flat, max_it, pro
     first) from the next round on, so that early members do not wait for the
     slowest one.  The slices' histograms are summed and ln g taken from the
     sum (ln g(E_min) = ln 2), which equals one production call of the same
-    sweeps.  Returns (attempts, iterations, ln g list, rounds, device ms)."""
+    sweeps.  Returns (attempts, iterations, ln g list, rounds, device ms of
+    every round)."""
     from paper_1707_00919_amd import MucaError
     from paper_1707_00919_amd.analysis import jackknife_log_dos
     members = [Solver(L, W, sd) for L, W, sd in inst]
@@ -364,7 +365,7 @@ def batched_solve(Batch, Solver, inst, flags, iter_sweeps, min_flat, max_it, pro
     therm_left = [prod_therm] * n
     prod_left = [prod_sweeps] * n
     acc = [np.zeros(m.N + 1, dtype=np.uint64) for m in members]
-    att, kernel_ms, rounds = 0, 0.0, 0
+    att, round_ms, rounds = 0, [], 0
     while any(ph != 2 for ph in phase):
         mode = np.zeros(n, dtype=np.uint32)
         th = np.zeros(n, dtype=np.uint32)
@@ -378,7 +379,7 @@ def batched_solve(Batch, Solver, inst, flags, iter_sweeps, min_flat, max_it, pro
                 sw[i] = min(prod_left[i], iter_sweeps - th[i])
         infos = b.run(mode, th, sw)
         rounds += 1
-        kernel_ms += next(i for i in infos if i is not None)["kernel_ms"]
+        round_ms.append(next(i for i in infos if i is not None)["kernel_ms"])
         for i, inf in enumerate(infos):
             if inf is None:
                 continue
@@ -403,7 +404,7 @@ def batched_solve(Batch, Solver, inst, flags, iter_sweeps, min_flat, max_it, pro
     b.close()
     for m in members:
         m.close()
-    return att, iters, lngs, rounds, kernel_ms
+    return att, iters, lngs, rounds, round_ms
 
 
 def bench_batched(args):
@@ -423,7 +424,9 @@ def bench_batched(args):
         batched()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    att_b, iters_b, lng_b, rounds, kms = batched()
+    att_b, iters_b, lng_b, rounds, round_ms = batched()
+    kms = float(sum(round_ms))
+    tenths = np.array_split(np.asarray(round_ms), 10)
     torch.cuda.synchronize()
     wall_b = time.perf_counter() - t0
     print("batched: %.2f s, %d rounds" % (wall_b, rounds), file=sys.stderr, flush=True)
@@ -464,6 +467,8 @@ def bench_batched(args):
                            "iterations": iters_s[slow]},
         "makespan_over_slowest_alone": wall_b / solo_wall[slow],
         "batched_device_ms": kms,
+        "device_share_of_wall": kms * 1e-3 / wall_b,
+        "round_device_ms_by_tenth": [round(float(t.mean()), 2) for t in tenths if t.size],
     }
     print(json.dumps(out), flush=True)
 
