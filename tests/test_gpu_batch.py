@@ -285,6 +285,41 @@ def test_batched_workload_full_size_sampled_walkers():
         np.testing.assert_array_equal(m.spins()[ids], o.spins)
 
 
+def test_batched_workload_full_size_iterations_match_oracle():
+    # the 48 instances at their full sizes in the benchmark's launch form
+    # (graph + autotune: the first round runs the mixed shape, the L = 48 and
+    # L = 64 members in pairs, the second a one-wave shape), two weight
+    # iterations of one unrecorded and one recorded sweep; every member's
+    # histogram and omega bit patterns, and every walker's spins and energy,
+    # against the oracle run on all walkers
+    from paper_1707_00919_amd import Batch, Solver, _abi
+    from muca_inputs import batch_instances
+    note("batched workload, full size, all walkers, two iterations")
+    inst = batch_instances()
+    members = [Solver(L, W, sd) for L, W, sd in inst]
+    oms = [smooth_log_weights(L, sd + 11) for L, _, sd in inst]
+    for m, om in zip(members, oms):
+        m.set_log_weights(om)
+    b = Batch(members, flags=_abi.MUCA_BATCH_GRAPH | _abi.MUCA_BATCH_AUTOTUNE)
+    hists, forms = [[] for _ in inst], set()
+    for _ in range(2):
+        infos = b.run([1] * len(members), 1, 1)
+        forms |= {i["kernel_variant"] for i in infos}
+        for k, m in enumerate(members):
+            hists[k].append(m.histogram())
+    assert 1 in forms and forms & {2, 5}
+    for k, ((L, W, sd), m, om) in enumerate(zip(inst, members, oms)):
+        o = oracle.OracleMuca(L, W, sd)
+        o.set_log_weights(om)
+        for r in range(2):
+            o.iterate(1, 1)
+            np.testing.assert_array_equal(hists[k][r], o.hist)
+        np.testing.assert_array_equal(bits(m.log_weights()), bits(o.omega))
+        np.testing.assert_array_equal(m.energies(), o.energies)
+        np.testing.assert_array_equal(m.spins(), o.spins)
+    b.close()
+
+
 def test_batch_member_with_zero_threshold_runs_generic():
     # a member whose table has a reachable T = 0 runs the generic kernel in
     # its own group, next to members on the other forms; all match their
