@@ -323,8 +323,8 @@ typedef struct muca_batch muca_batch;
                                      four launch shapes on four such rounds and
                                      keep the fastest -- the mixed shape (the
                                      two-wave form for the members with the
-                                     fewest walkers, as many as fit, the
-                                     one-wave form for the rest), the one-wave
+                                     longest chains per round, as many as fit,
+                                     the one-wave form for the rest), the one-wave
                                      form with its default walkers per
                                      workgroup, the one-wave form with 256
                                      walkers (four waves) sharing each
@@ -332,9 +332,12 @@ typedef struct muca_batch muca_batch;
                                      the histograms merged twice per round (two
                                      launches) -- and time them again once the
                                      rounds' walkers have halved; rounds that
-                                     fit run the two-wave form, and without the
-                                     flag the others run the mixed shape;
-                                     results do not depend on the choice        */
+                                     fit run the two-wave form (at L = 48-64 in
+                                     pairs of chains sharing one table where
+                                     one workgroup per chain does not fit), and
+                                     without the flag the others run the mixed
+                                     shape; results do not depend on the
+                                     choice                                    */
 
 /* Group count live instances.  members[] stay owned by the caller and must
  * outlive the batch; they are not to be called while a round runs, and all

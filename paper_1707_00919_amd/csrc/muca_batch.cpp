@@ -51,16 +51,18 @@ struct Group {
 };
 
 // Launch shapes of a round, for members that can run the LDS-record kernels:
-// the two-wave form for all; the one-wave form with its default wave groups,
-// or with four waves (256 walkers) sharing each table; the mixed shape -- the
-// two-wave form for the members with the fewest walkers, as many as fit on the
-// device at once, the one-wave form for the others; and the histogram-merge
-// cadence -- the round's default shape with its sweeps cut into two launches,
-// so that every workgroup's LDS counters are merged into the global histogram
-// twice per round instead of once.  A round whose two-wave workgroups all fit
-// runs the two-wave form; the others run the mixed shape, or with the
-// autotuner the fastest of the last four, timed on four rounds and timed again
-// once the rounds' walkers have halved since.
+// the two-wave form for all (at L = 48-64 in pairs, two chains per table,
+// where one workgroup per chain does not fit); the one-wave form with its
+// default wave groups, or with four waves (256 walkers) sharing each table;
+// the mixed shape -- the two-wave form for the members with the longest
+// chains per round, as many as fit on the device at once, the one-wave form
+// for the others; and the histogram-merge cadence -- the round's default
+// shape with its sweeps cut into two launches, so that every workgroup's LDS
+// counters are merged into the global histogram twice per round instead of
+// once.  A round whose two-wave workgroups all fit runs the two-wave form; the
+// others run the mixed shape, or with the autotuner the fastest of the last
+// four, timed on four rounds and timed again once the rounds' walkers have
+// halved since.
 constexpr int kChoices = 5;
 constexpr int kTwoWave = 0, kOneWaveDefault = 1, kOneWaveFour = 2, kTwoMerges = 3, kMixed = 4;
 constexpr int kTuned[4] = {kMixed, kOneWaveDefault, kOneWaveFour, kTwoMerges};
