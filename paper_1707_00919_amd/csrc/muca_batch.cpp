@@ -40,7 +40,8 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 thread_local std::string g_batch_error;
 
 // kernel forms, as in muca_info::kernel_variant
-constexpr uint32_t kGeneric = 0, kFast = 1, kSplit = 2, kWide = 3, kWideSplit = 4, kPair = 5;
+constexpr uint32_t kGeneric = muca_host::kFormGeneric, kFast = muca_host::kFormFast, kSplit = muca_host::kFormSplit,
+                   kWide = muca_host::kFormWide, kWideSplit = muca_host::kFormWideSplit, kPair = muca_host::kFormPair;
 
 struct Group {
     uint32_t L = 0;
@@ -64,7 +65,8 @@ struct Group {
 // four, timed on four rounds and timed again once the rounds' walkers have
 // halved since.
 constexpr int kChoices = 5;
-constexpr int kTwoWave = 0, kOneWaveDefault = 1, kOneWaveFour = 2, kTwoMerges = 3, kMixed = 4;
+constexpr int kTwoWave = muca_host::kShapeTwoWave, kOneWaveDefault = muca_host::kShapeOneWave,
+              kOneWaveFour = muca_host::kShapeOneWaveFour, kTwoMerges = 3, kMixed = muca_host::kShapeMixed;
 constexpr int kTuned[4] = {kMixed, kOneWaveDefault, kOneWaveFour, kTwoMerges};
 
 }  // namespace
@@ -497,44 +499,35 @@ static int muca_batch_submit_impl(muca_batch* b, const uint32_t* mode, const uin
         BATCH_HIP(b, hipEventRecord(b->ev_done, b->stream), "hipEventRecord");
         return MUCA_OK;
     }
-    // two-wave form while all of the batch's two-wave workgroups fit on the
-    // device at once, at most two chains per CU (LDS shares weighted by each
-    // L): with one workgroup each, or else with the pair form (two chains
-    // sharing one table) for the members whose workgroup fills a CU
-    std::vector<double> share(count, 0.0), share_pair(count, 0.0);
-    std::vector<char> pairable(count, 0);
-    double lds_share = 0.0, lds_share_pair = 0.0;
-    uint64_t walkers = 0;
+    // the round's launch plan (muca_host::round_fit / plan_forms): the
+    // two-wave form while all of its workgroups fit on the device at once,
+    // single or in pairs; otherwise the mixed shape, or with the autotuner
+    // the shape it picks
+    std::vector<muca_host::RoundMember> rm(count);
     for (uint32_t i = 0; i < count; ++i) {
         if (mode[i] == MUCA_BATCH_SKIP)
             continue;
-        walkers += b->m[i]->p.walkers;
-        const uint32_t L = b->m[i]->L;
-        const double nb = (double)(b->m[i]->wpad / muca::kWave);
-        uint32_t bytes = 0;
-        if (form[i] == kFast && muca::split_sweep_supported(L))
-            bytes = muca::split_lds_bytes(L);
-        else if (form[i] == kWide && muca::wide_split_supported(L))
-            bytes = muca::wide_split_lds_bytes(L);
-        if (bytes)
-            share[i] = nb * std::max(0.5, 1.0 / (double)(muca::kLdsPerCu / bytes));
-        share_pair[i] = share[i];
-        if (form[i] == kFast && muca::pair_sweep_supported(L) &&
-            muca::split_groups_per_cu(muca::split_lds_bytes(L)) == 1u &&
-            !(b->m[i]->p.flags & MUCA_FLAG_FAST_KERNEL)) {
-            pairable[i] = 1;
-            share_pair[i] = 0.5 * nb;
-        }
-        lds_share += share[i];
-        lds_share_pair += share_pair[i];
+        const muca_instance* h = b->m[i];
+        muca_host::RoundMember& r = rm[i];
+        r.active = true;
+        r.L = h->L;
+        r.blocks = h->wpad / muca::kWave;
+        r.walkers = h->p.walkers;
+        r.chain = (uint64_t)h->N * total[i];
+        r.table = form[i];
+        r.forced_fast = (h->p.flags & MUCA_FLAG_FAST_KERNEL) != 0;
+        r.split_ok = muca::split_sweep_supported(h->L);
+        r.fast_ok = muca::fast_sweep_supported(h->L);
+        r.pair_ok = muca::pair_sweep_supported(h->L);
+        r.wide_split_ok = muca::wide_split_supported(h->L);
+        r.two_wave_bytes = form[i] == kFast && r.split_ok       ? muca::split_lds_bytes(h->L)
+                           : form[i] == kWide && r.wide_split_ok ? muca::wide_split_lds_bytes(h->L)
+                                                                 : 0u;
+        r.fast_waves = r.fast_ok ? muca::fast_waves_per_group(h->L) : 1u;
     }
-    const bool fits_blocks = active_blocks <= 2u * (uint32_t)b->cus;
-    const bool two_wave_single = fits_blocks && lds_share <= (double)b->cus;
-    const bool two_wave = two_wave_single || (fits_blocks && lds_share_pair <= (double)b->cus);
-    // pairs wherever a round does not fit with one workgroup per chain
-    const bool use_pairs = !two_wave_single;
-    if (use_pairs)
-        share = share_pair;
+    const muca_host::RoundFit fit = muca_host::round_fit(rm.data(), count, (uint32_t)b->cus, muca::kLdsPerCu);
+    const bool two_wave = fit.two_wave;
+    const uint64_t walkers = fit.walkers;
     b->tuning = false;
     b->round_walkers = walkers;
     if (two_wave) {
@@ -551,53 +544,10 @@ static int muca_batch_submit_impl(muca_batch* b, const uint32_t* mode, const uin
     }
     // the kernel form of the choice (the merge-cadence choice keeps the default shape)
     const int shape = b->choice == kTwoMerges ? (two_wave ? kTwoWave : kMixed) : b->choice;
-    // members in the two-wave form: all, or (mixed) as many as fit, those
-    // with the longest chains first -- a round lasts as long as its longest
-    // chain (sites x sweeps of one walker), which the two-wave form shortens
-    // most -- and among equal chains those with the fewest walkers: a
-    // population with fewer walkers needs more weight iterations, so its
-    // chains are the ones later rounds wait for, and it costs the least room
-    std::vector<char> two(count, 0);
-    if (shape == kTwoWave) {
-        std::fill(two.begin(), two.end(), 1);
-    } else if (shape == kMixed) {
-        std::vector<uint32_t> order;
-        for (uint32_t i = 0; i < count; ++i)
-            if (mode[i] != MUCA_BATCH_SKIP && share[i] > 0.0)
-                order.push_back(i);
-        std::stable_sort(order.begin(), order.end(), [&](uint32_t x, uint32_t y) {
-            const uint64_t cx = (uint64_t)b->m[x]->N * total[x], cy = (uint64_t)b->m[y]->N * total[y];
-            return cx != cy ? cx > cy : b->m[x]->p.walkers < b->m[y]->p.walkers;
-        });
-        double used = 0.0;
-        size_t blocks = 0;
-        for (uint32_t i : order) {
-            const size_t nb = b->m[i]->wpad / muca::kWave;
-            if (used + share[i] > (double)b->cus || blocks + nb > 2u * (size_t)b->cus)
-                break;
-            used += share[i];
-            blocks += nb;
-            two[i] = 1;
-        }
-    }
     std::vector<uint32_t> waves(count, 1u);
+    muca_host::plan_forms(rm.data(), count, (uint32_t)b->cus, fit, shape, form.data(), waves.data());
     for (uint32_t i = 0; i < count; ++i) {
         const uint32_t L = b->m[i]->L;
-        if (form[i] == kWide && two[i] && !(b->m[i]->p.flags & MUCA_FLAG_FAST_KERNEL) &&
-            muca::wide_split_supported(L))
-            form[i] = kWideSplit;  // the same tables, Philox on a second wave
-        if (form[i] == kFast) {
-            const bool want_fast = (b->m[i]->p.flags & MUCA_FLAG_FAST_KERNEL) != 0 || !two[i];
-            if (two[i] && use_pairs && pairable[i]) {
-                form[i] = kPair;
-                waves[i] = 2u;  // two chains count into one table
-            } else if (muca::split_sweep_supported(L) && !(want_fast && muca::fast_sweep_supported(L))) {
-                form[i] = kSplit;
-            } else {
-                form[i] = kFast;
-                waves[i] = shape == kOneWaveFour ? 4u : muca::fast_waves_per_group(L);
-            }
-        }
         // a launch stays below 2^32 counts per LDS counter of a workgroup
         if (mode[i] != MUCA_BATCH_SKIP)
             chunk = std::min(chunk, muca::max_sweeps_per_launch(L, waves[i]));

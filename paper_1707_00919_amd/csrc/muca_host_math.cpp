@@ -229,6 +229,92 @@ double solve_work_estimate(uint32_t L, uint32_t walkers, uint32_t iter_therm, ui
     return (double)walkers * n * sweeps;
 }
 
+RoundFit round_fit(const RoundMember* m, size_t n, uint32_t cus, uint32_t lds_per_cu)
+{
+    RoundFit fit;
+    fit.share.assign(n, 0.0);
+    fit.pairable.assign(n, 0);
+    std::vector<double>& share = fit.share;
+    uint64_t blocks = 0;
+    double single = 0.0, paired = 0.0;
+    std::vector<double> share_pair(n, 0.0);
+    for (size_t i = 0; i < n; ++i) {
+        if (!m[i].active)
+            continue;
+        fit.walkers += m[i].walkers;
+        blocks += m[i].blocks;
+        const double nb = (double)m[i].blocks;
+        const bool two_capable = (m[i].table == kFormFast && m[i].split_ok) ||
+                                 (m[i].table == kFormWide && m[i].wide_split_ok);
+        if (two_capable && m[i].two_wave_bytes > 0 && m[i].two_wave_bytes <= lds_per_cu)
+            share[i] = nb * std::max(0.5, 1.0 / (double)(lds_per_cu / m[i].two_wave_bytes));
+        share_pair[i] = share[i];
+        if (m[i].table == kFormFast && m[i].pair_ok && !m[i].forced_fast && share[i] > 0.0 &&
+            lds_per_cu / m[i].two_wave_bytes == 1u) {
+            fit.pairable[i] = 1;
+            share_pair[i] = 0.5 * nb;
+        }
+        single += share[i];
+        paired += share_pair[i];
+    }
+    const bool fits_blocks = blocks <= 2u * (uint64_t)cus;
+    fit.two_wave_single = fits_blocks && single <= (double)cus;
+    fit.two_wave = fit.two_wave_single || (fits_blocks && paired <= (double)cus);
+    fit.use_pairs = !fit.two_wave_single;
+    if (fit.use_pairs)
+        for (size_t i = 0; i < n; ++i)
+            share[i] = share_pair[i];
+    return fit;
+}
+
+void plan_forms(const RoundMember* m, size_t n, uint32_t cus, const RoundFit& fit, int shape, uint32_t* form,
+                uint32_t* waves)
+{
+    const std::vector<double>& share = fit.share;
+    std::vector<char> two(n, 0);
+    if (shape == kShapeTwoWave) {
+        std::fill(two.begin(), two.end(), 1);
+    } else if (shape == kShapeMixed) {
+        std::vector<size_t> order;
+        for (size_t i = 0; i < n; ++i)
+            if (m[i].active && share[i] > 0.0)
+                order.push_back(i);
+        std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) {
+            return m[x].chain != m[y].chain ? m[x].chain > m[y].chain : m[x].walkers < m[y].walkers;
+        });
+        double used = 0.0;
+        uint64_t blocks = 0;
+        for (size_t i : order) {
+            if (used + share[i] > (double)cus || blocks + m[i].blocks > 2u * (uint64_t)cus)
+                break;
+            used += share[i];
+            blocks += m[i].blocks;
+            two[i] = 1;
+        }
+    }
+    for (size_t i = 0; i < n; ++i) {
+        form[i] = kFormGeneric;
+        waves[i] = 1u;
+        if (!m[i].active)
+            continue;
+        form[i] = m[i].table;
+        if (m[i].table == kFormWide && two[i] && !m[i].forced_fast && m[i].wide_split_ok)
+            form[i] = kFormWideSplit;  // the same tables, Philox on a second wave
+        if (m[i].table == kFormFast) {
+            const bool want_fast = m[i].forced_fast || !two[i];
+            if (two[i] && fit.use_pairs && fit.pairable[i]) {
+                form[i] = kFormPair;
+                waves[i] = 2u;  // two chains count into one table
+            } else if (m[i].split_ok && !(want_fast && m[i].fast_ok)) {
+                form[i] = kFormSplit;
+            } else {
+                form[i] = kFormFast;
+                waves[i] = shape == kShapeOneWaveFour ? 4u : m[i].fast_waves;
+            }
+        }
+    }
+}
+
 size_t admission_pick(const QueuedJob* q, size_t n, bool smallest_first, double now, double max_wait_s)
 {
     if (n == 0 || !smallest_first)

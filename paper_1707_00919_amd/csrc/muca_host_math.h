@@ -48,6 +48,52 @@ struct Segment {
 // sweeps for the range kernel.
 std::vector<Segment> segments_of(uint64_t N, uint64_t pos0, uint64_t therm, uint64_t recorded);
 
+// Launch planning of one batched round (no device involved).  Forms are
+// numbered as muca_info::kernel_variant: 0 generic, 1 one-wave (fast), 2
+// two-wave (split), 3 wide one-wave, 4 wide two-wave, 5 two-wave pairs.
+enum : uint32_t { kFormGeneric = 0, kFormFast = 1, kFormSplit = 2, kFormWide = 3, kFormWideSplit = 4, kFormPair = 5 };
+// Launch shapes: two-wave for all, one-wave with default wave groups, one-wave
+// with four waves per table, mixed.
+enum : int { kShapeTwoWave = 0, kShapeOneWave = 1, kShapeOneWaveFour = 2, kShapeMixed = 4 };
+
+// One member of a round as the planner sees it.  table: the table the member's
+// weights allow this round -- kFormFast (the LDS-record kernels), kFormWide or
+// kFormGeneric.
+struct RoundMember {
+    bool active = false;        // not skipped this round
+    uint32_t L = 0;
+    uint32_t blocks = 0;        // 64-walker blocks
+    uint32_t walkers = 0;
+    uint64_t chain = 0;         // attempts one walker makes this round
+    uint32_t table = kFormGeneric;
+    bool forced_fast = false;   // MUCA_FLAG_FAST_KERNEL
+    bool split_ok = false, fast_ok = false, pair_ok = false, wide_split_ok = false;
+    uint32_t two_wave_bytes = 0;   // LDS of one two-wave workgroup (split or wide split), 0: none
+    uint32_t fast_waves = 1;       // waves per workgroup of the one-wave form by default
+};
+
+// Whether a round's two-wave workgroups all fit on the device at once, at
+// most two chains per CU (LDS shares weighted by each L): with one workgroup
+// per chain (single), or with pairs for the members whose split workgroup
+// fills a CU (pairable).  share[i]: member i's share of the CUs in the
+// arrangement used (pairs wherever single does not fit); 0 if it has no
+// two-wave form.
+struct RoundFit {
+    bool two_wave_single = false;
+    bool two_wave = false;
+    bool use_pairs = false;
+    uint64_t walkers = 0;
+    std::vector<double> share;
+    std::vector<char> pairable;
+};
+RoundFit round_fit(const RoundMember* m, size_t n, uint32_t cus, uint32_t lds_per_cu);
+
+// Forms and waves per workgroup of every member for a launch shape; in the
+// mixed shape the two-wave form goes to the members with the longest chains
+// (then the fewest walkers) while their shares fit.
+void plan_forms(const RoundMember* m, size_t n, uint32_t cus, const RoundFit& fit, int shape, uint32_t* form,
+                uint32_t* waves);
+
 // Estimated attempts of one served solve: walkers * N per sweep, times the
 // sweeps it asks for -- its weight iterations of iter_therm + iter_sweeps
 // sweeps each, then prod_therm + prod_sweeps.  The number of iterations to a
