@@ -6,9 +6,10 @@
 // acceptance min(1, exp[omega(E') - omega(E)]) as an integer threshold), with
 // the per-attempt work cut to what the method needs:
 //
-//  * Bond words (muca_rowbits.h): the number m of anti-aligned neighbours of a
-//    site is one popcount and one bit-field extract, and the row's flipped
-//    sites are recovered at the row's end.
+//  * Site words (muca_rowbits.h): per group of eight sites one word of the
+//    row's bonds and vertical mismatches, so that a site's count of
+//    anti-aligned neighbours is one masked popcount; the row's flips are
+//    collected as a word and applied at the row's end.
 //  * One 28-byte LDS record per energy bin and a chain step that loads both
 //    thresholds the next attempt can need while the current one is decided
 //    (muca_chain.h).

@@ -8,20 +8,24 @@
 // shortens it in two ways:
 //
 //  * A workgroup has two waves for the same 64 walkers.  The producer wave
-//    runs Philox4x32-10 for the next loop step (one row, or two when L is not
-//    a multiple of 4) and writes the words to an LDS ring; the consumer wave
-//    runs only the chain, reading four draws with one 16-byte LDS load.  One
-//    barrier per loop step hands a ring slot over.
+//    runs Philox4x32-10 for the next loop step (one to four rows, or half a
+//    row in the pair form at L = 64) and writes the words to an LDS ring; the
+//    consumer wave runs only the chain, reading four draws with one 16-byte
+//    LDS load.  One barrier per loop step hands a ring slot over.
 //  * The consumer's chain step (muca_chain.h) resolves attempt x while the two
 //    thresholds attempt x+1 can need are already on their way.
 //
+// The pair form (L = 48..64, where one such workgroup fills a CU's LDS) puts
+// two chain waves and their two producer waves in one workgroup around one
+// record table, so that a CU runs two chains.
+//
 // For L <= 64 the per-bin records live in LDS: 28 bytes (7 words: the five
-// thresholds S = T - 1 by the number m of anti-aligned neighbours, the
-// histogram counter, one pad word); an odd word stride spreads the gathers of
-// 64 lanes over all banks.  For L = 80..128 (the wide form) the records do not
-// fit: the chain reads the 32-byte threshold records from global memory through
-// the caches and LDS holds only the 32-bit counters in front of the ring.
-// The row bookkeeping (bond words, vertical fields) is in muca_rowbits.h.
+// thresholds S = T - 1 by the number m of anti-aligned neighbours, from m = 4
+// down, the histogram counter, one pad word); an odd word stride spreads the
+// gathers of 64 lanes over all banks.  For L = 80..128 (the wide form) the
+// records do not fit: the chain reads the 32-byte threshold records from
+// global memory through the caches and LDS holds only the 32-bit counters in
+// front of the ring.  The row bookkeeping (site words) is in muca_rowbits.h.
 #include <type_traits>
 
 #include "muca_device.h"

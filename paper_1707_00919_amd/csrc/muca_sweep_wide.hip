@@ -5,7 +5,7 @@
 // next attempt can need are loaded while the current attempt is decided, so
 // one load latency is hidden per attempt), with the threshold records --
 // 32 bytes per energy bin, the five thresholds S = T - 1 by the number m of
-// anti-aligned neighbours -- read from global memory through the caches (the
+// anti-aligned neighbours, from m = 4 down -- read from global memory through the caches (the
 // table, 512 KiB at L = 128, stays in L2), and only the 32-bit histogram
 // counters in LDS (64 KiB + 4 B at L = 128).  One wave per 64 walkers,
 // Philox4x32-10 computed in place.  Used when no reachable threshold is 0
