@@ -2,8 +2,8 @@
 tests (a slow device must not hide them).
 
 The sweep rate at L = 32 with 16384 walkers at the exact weights (the paper's
-hardware measurement, Sec. 3.1) stays above 2.5e11 attempts/s, about three
-quarters of what the kernel reaches on an MI355X: a guard against a
+hardware measurement, Sec. 3.1) stays above 3.0e11 attempts/s, about three
+quarters of what the kernel reaches on an MI355X (4.1e11): a guard against a
 performance regression, not a measurement (bench.py measures).
 """
 import math
@@ -48,5 +48,5 @@ def test_sweep_rate_floor_at_the_papers_scale():
     info = s.production(0, 200)
     rate = info["attempts"] / (info["kernel_ms"] * 1e-3)
     note("  %.3e attempts/s (kernel variant %d)" % (rate, info["kernel_variant"]))
-    assert rate > 2.5e11
+    assert rate > 3.0e11
     s.close()
