@@ -320,24 +320,26 @@ typedef struct muca_batch muca_batch;
                                      run without the graph                     */
 #define MUCA_BATCH_AUTOTUNE 0x2u  /* for rounds whose two-wave workgroups do
                                      not all fit on the device at once, time
-                                     four launch shapes on four such rounds and
-                                     keep the fastest -- the mixed shape (the
-                                     two-wave form for the members with the
-                                     longest chains per round, as many as fit,
-                                     the one-wave form for the rest), the one-wave
-                                     form with its default walkers per
-                                     workgroup, the one-wave form with 256
+                                     five launch shapes on five such rounds and
+                                     keep the fastest -- the mixed-longest shape
+                                     (the two-wave form only for the members
+                                     whose chain is the round's longest, the
+                                     one-wave form for the rest), the mixed
+                                     shape (the two-wave form for the members
+                                     with the longest chains, as many as fit),
+                                     the one-wave form with its default walkers
+                                     per workgroup, the one-wave form with 256
                                      walkers (four waves) sharing each
-                                     threshold table, and the mixed shape with
-                                     the histograms merged twice per round (two
-                                     launches) -- and time them again once the
-                                     rounds' walkers have halved; rounds that
-                                     fit run the two-wave form (at L = 48-64 in
-                                     pairs of chains sharing one table where
-                                     one workgroup per chain does not fit), and
-                                     without the flag the others run the mixed
-                                     shape; results do not depend on the
-                                     choice                                    */
+                                     threshold table, and the mixed-longest
+                                     shape with the histograms merged twice per
+                                     round (two launches) -- and time them again
+                                     once the rounds' walkers have halved;
+                                     rounds that fit run the two-wave form (at
+                                     L = 48-64 in pairs of chains sharing one
+                                     table where one workgroup per chain does
+                                     not fit), and without the flag the others
+                                     run the mixed-longest shape; results do not
+                                     depend on the choice                      */
 
 /* Group count live instances.  members[] stay owned by the caller and must
  * outlive the batch; they are not to be called while a round runs, and all

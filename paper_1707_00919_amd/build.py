@@ -21,7 +21,8 @@ LIB = os.path.join(HERE, "libmuca.so")
 ARCH = "gfx950"
 
 SOURCES = ["muca_kernels.hip", "muca_sweep_fast.hip", "muca_sweep_split.hip", "muca_sweep_wide.hip", "muca_runtime.cpp",
-           "muca_host_math.cpp", "muca_batch.cpp", "muca_server.cpp", "muca_analysis.cpp", "muca_probe.hip", "muca_static.hip"]
+           "muca_host_math.cpp", "muca_batch.cpp", "muca_server.cpp", "muca_analysis.cpp", "muca_probe.hip", "muca_static.hip",
+           "muca_order.hip"]
 COMMON = [
     "-O3", "-std=c++17", "-fPIC", "-Wall",
     "-ffp-contract=off", "-fno-fast-math",

@@ -43,12 +43,22 @@ thread_local std::string g_batch_error;
 constexpr uint32_t kGeneric = muca_host::kFormGeneric, kFast = muca_host::kFormFast, kSplit = muca_host::kFormSplit,
                    kWide = muca_host::kFormWide, kWideSplit = muca_host::kFormWideSplit, kPair = muca_host::kFormPair;
 
+bool two_wave_form(uint32_t form) { return form == kSplit || form == kPair || form == kWideSplit; }
+
+// A round's launches are issued longest chains first -- the two-wave groups,
+// then the others, each kind by its longest chain -- and each one after the
+// first behind a wait of this many microseconds more than the one before, long
+// enough for the earlier launches to have placed their workgroups
+// (muca_order.hip).
+constexpr uint32_t kDispatchDelayUs = 30;
+
 struct Group {
     uint32_t L = 0;
     uint32_t form = kGeneric;
     uint32_t waves = 1;       // waves of 64 walkers per workgroup (one-wave form)
     uint32_t first_item = 0;  // index into the items array
     uint32_t nitems = 0;
+    uint64_t chain = 0;       // attempts of the group's longest walker chain
 };
 
 // Launch shapes of a round, for members that can run the LDS-record kernels:
@@ -57,17 +67,22 @@ struct Group {
 // default wave groups, or with four waves (256 walkers) sharing each table;
 // the mixed shape -- the two-wave form for the members with the longest
 // chains per round, as many as fit on the device at once, the one-wave form
-// for the others; and the histogram-merge cadence -- the round's default
-// shape with its sweeps cut into two launches, so that every workgroup's LDS
-// counters are merged into the global histogram twice per round instead of
-// once.  A round whose two-wave workgroups all fit runs the two-wave form; the
-// others run the mixed shape, or with the autotuner the fastest of the last
-// four, timed on four rounds and timed again once the rounds' walkers have
-// halved since.
-constexpr int kChoices = 5;
+// for the others; the mixed-longest shape -- the two-wave form only for the
+// members whose chain is the round's longest, so that the shorter chains start
+// at once on the CUs those leave, instead of waiting for a CU that the
+// two-wave workgroups of the next-longest hold; and the histogram-merge
+// cadence -- the round's default shape with its sweeps cut into two launches,
+// so that every workgroup's LDS counters are merged into the global histogram
+// twice per round instead of once.  A round whose two-wave workgroups all fit
+// runs the two-wave form; the others run the mixed-longest shape, or with the
+// autotuner the fastest of the last five, timed on five rounds and timed again
+// once the rounds' walkers have halved since.
+constexpr int kChoices = 6;
 constexpr int kTwoWave = muca_host::kShapeTwoWave, kOneWaveDefault = muca_host::kShapeOneWave,
-              kOneWaveFour = muca_host::kShapeOneWaveFour, kTwoMerges = 3, kMixed = muca_host::kShapeMixed;
-constexpr int kTuned[4] = {kMixed, kOneWaveDefault, kOneWaveFour, kTwoMerges};
+              kOneWaveFour = muca_host::kShapeOneWaveFour, kTwoMerges = 3, kMixed = muca_host::kShapeMixed,
+              kMixedLongest = muca_host::kShapeMixedLongest;
+constexpr int kTuned[5] = {kMixedLongest, kMixed, kOneWaveDefault, kOneWaveFour, kTwoMerges};
+constexpr uint32_t kNumTuned = sizeof(kTuned) / sizeof(kTuned[0]);
 
 }  // namespace
 
@@ -109,7 +124,7 @@ struct muca_batch {
     // autotuner: attempts/ms of the shapes timed so far (rounds whose
     // two-wave workgroups do not all fit)
     uint32_t round = 0;
-    double tuned_rate[kChoices] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    double tuned_rate[kChoices] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     int tuned_form = -1;
     uint32_t tune_step = 0;        // shapes timed since the last (re)start
     uint64_t tuned_walkers = 0;    // walkers of the round the choice was made on
@@ -208,10 +223,14 @@ int enqueue_round(muca_batch* b, size_t stage_used, const std::vector<Group>& gr
     const auto* fargs = reinterpret_cast<const muca::FastSweepArgs*>(ds + b->off_fargs);
     const auto* gargs = reinterpret_cast<const muca::SweepArgs*>(ds + b->off_gargs);
     const auto* items = reinterpret_cast<const muca::BatchItem*>(ds + b->off_items);
+    // groups come in dispatch order (muca_batch_submit): each after the first
+    // waits a little longer than the one before
     for (size_t g = 0; g < groups.size(); ++g) {
         const Group& G = groups[g];
         hipStream_t s = b->gstreams[g];
         BATCH_HIP(b, hipStreamWaitEvent(s, b->ev_fork, 0), "hipStreamWaitEvent");
+        if (g > 0)
+            BATCH_HIP(b, muca::launch_dispatch_delay((uint32_t)g * kDispatchDelayUs, s), "dispatch delay");
         hipError_t e;
         if (G.form == kSplit)
             e = muca::launch_split_batch(G.L, fargs, items + G.first_item, G.nitems, s);
@@ -501,8 +520,8 @@ static int muca_batch_submit_impl(muca_batch* b, const uint32_t* mode, const uin
     }
     // the round's launch plan (muca_host::round_fit / plan_forms): the
     // two-wave form while all of its workgroups fit on the device at once,
-    // single or in pairs; otherwise the mixed shape, or with the autotuner
-    // the shape it picks
+    // single or in pairs; otherwise the mixed-longest shape, or with the
+    // autotuner the shape it picks
     std::vector<muca_host::RoundMember> rm(count);
     for (uint32_t i = 0; i < count; ++i) {
         if (mode[i] == MUCA_BATCH_SKIP)
@@ -538,12 +557,12 @@ static int muca_batch_submit_impl(muca_batch* b, const uint32_t* mode, const uin
             b->tune_step = 0;
         }
         b->tuning = b->tuned_form < 0;
-        b->choice = b->tuning ? kTuned[b->tune_step % 4] : b->tuned_form;
+        b->choice = b->tuning ? kTuned[b->tune_step % kNumTuned] : b->tuned_form;
     } else {
-        b->choice = kMixed;
+        b->choice = kMixedLongest;
     }
     // the kernel form of the choice (the merge-cadence choice keeps the default shape)
-    const int shape = b->choice == kTwoMerges ? (two_wave ? kTwoWave : kMixed) : b->choice;
+    const int shape = b->choice == kTwoMerges ? (two_wave ? kTwoWave : kMixedLongest) : b->choice;
     std::vector<uint32_t> waves(count, 1u);
     muca_host::plan_forms(rm.data(), count, (uint32_t)b->cus, fit, shape, form.data(), waves.data());
     for (uint32_t i = 0; i < count; ++i) {
@@ -581,11 +600,18 @@ static int muca_batch_submit_impl(muca_batch* b, const uint32_t* mode, const uin
             for (uint32_t blk = 0; blk < (blocks + per - 1) / per; ++blk)
                 items[nitems++] = muca::BatchItem{i, blk};
             key += std::to_string(i) + ":" + std::to_string(total[i]) + ",";
+            G.chain = std::max(G.chain, (uint64_t)b->m[i]->N * total[i]);
         }
         G.nitems = nitems - G.first_item;
         key += "|" + std::to_string(G.L) + "/" + std::to_string(G.form) + "/" + std::to_string(G.waves) + ";";
         groups.push_back(G);
     }
+    // dispatch order: two-wave groups first, then the others, each kind by its
+    // longest chain (muca_order.hip)
+    std::stable_sort(groups.begin(), groups.end(), [](const Group& x, const Group& y) {
+        const bool tx = two_wave_form(x.form), ty = two_wave_form(y.form);
+        return tx != ty ? tx : x.chain > y.chain;
+    });
     if (int rc = ensure_group_streams(b, groups.size()))
         return rc;
     const size_t stage_used = b->stage_bytes;
@@ -790,7 +816,7 @@ int muca_batch_finish(muca_batch* b, muca_info* infos)
     }
     if (b->launches && b->tuning && ms > 0.0f) {
         b->tuned_rate[b->choice] = (double)attempts / ms;
-        if (++b->tune_step >= 4u) {
+        if (++b->tune_step >= kNumTuned) {
             int best = kTuned[0];
             for (int c : kTuned)
                 if (b->tuned_rate[c] > b->tuned_rate[best])

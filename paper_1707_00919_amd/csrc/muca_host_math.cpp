@@ -274,7 +274,7 @@ void plan_forms(const RoundMember* m, size_t n, uint32_t cus, const RoundFit& fi
     std::vector<char> two(n, 0);
     if (shape == kShapeTwoWave) {
         std::fill(two.begin(), two.end(), 1);
-    } else if (shape == kShapeMixed) {
+    } else if (shape == kShapeMixed || shape == kShapeMixedLongest) {
         std::vector<size_t> order;
         for (size_t i = 0; i < n; ++i)
             if (m[i].active && share[i] > 0.0)
@@ -285,6 +285,10 @@ void plan_forms(const RoundMember* m, size_t n, uint32_t cus, const RoundFit& fi
         double used = 0.0;
         uint64_t blocks = 0;
         for (size_t i : order) {
+            // mixed-longest: the two-wave form for the longest chains alone, so
+            // that the shorter ones start at once on the CUs left over
+            if (shape == kShapeMixedLongest && m[i].chain < m[order.front()].chain)
+                break;
             if (used + share[i] > (double)cus || blocks + m[i].blocks > 2u * (uint64_t)cus)
                 break;
             used += share[i];

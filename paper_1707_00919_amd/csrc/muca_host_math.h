@@ -53,8 +53,9 @@ std::vector<Segment> segments_of(uint64_t N, uint64_t pos0, uint64_t therm, uint
 // two-wave (split), 3 wide one-wave, 4 wide two-wave, 5 two-wave pairs.
 enum : uint32_t { kFormGeneric = 0, kFormFast = 1, kFormSplit = 2, kFormWide = 3, kFormWideSplit = 4, kFormPair = 5 };
 // Launch shapes: two-wave for all, one-wave with default wave groups, one-wave
-// with four waves per table, mixed.
-enum : int { kShapeTwoWave = 0, kShapeOneWave = 1, kShapeOneWaveFour = 2, kShapeMixed = 4 };
+// with four waves per table, mixed (the longest chains first, as many as fit),
+// mixed-longest (only the members whose chain is the round's longest).
+enum : int { kShapeTwoWave = 0, kShapeOneWave = 1, kShapeOneWaveFour = 2, kShapeMixed = 4, kShapeMixedLongest = 5 };
 
 // One member of a round as the planner sees it.  table: the table the member's
 // weights allow this round -- kFormFast (the LDS-record kernels), kFormWide or
@@ -90,7 +91,8 @@ RoundFit round_fit(const RoundMember* m, size_t n, uint32_t cus, uint32_t lds_pe
 
 // Forms and waves per workgroup of every member for a launch shape; in the
 // mixed shape the two-wave form goes to the members with the longest chains
-// (then the fewest walkers) while their shares fit.
+// (then the fewest walkers) while their shares fit, in the mixed-longest
+// shape only to those whose chain equals the round's longest.
 void plan_forms(const RoundMember* m, size_t n, uint32_t cus, const RoundFit& fit, int shape, uint32_t* form,
                 uint32_t* waves);
 

@@ -13,6 +13,13 @@
 #include "muca.h"
 #include "muca_host_math.h"
 
+namespace muca {
+// A wait of about `microseconds` on stream s, in front of a batched round's
+// one-wave launches so that its two-wave launches are dispatched first
+// (muca_order.hip).
+hipError_t launch_dispatch_delay(uint32_t microseconds, hipStream_t s);
+}  // namespace muca
+
 namespace muca_host {
 
 struct Layout {

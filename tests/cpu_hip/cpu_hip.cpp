@@ -810,6 +810,15 @@ hipError_t launch_init(const InitArgs& a, hipStream_t s)
     return hipSuccess;
 }
 
+hipError_t launch_dispatch_delay(uint32_t microseconds, hipStream_t s)
+{
+    if (microseconds)
+        submit(resolve(s), [microseconds] {
+            std::this_thread::sleep_for(std::chrono::microseconds(microseconds));
+        });
+    return hipSuccess;
+}
+
 hipError_t launch_fill_u64(unsigned long long* p, size_t n, hipStream_t s)
 {
     check_range(p, n * sizeof(uint64_t), kDevice, "fill: out of bounds");

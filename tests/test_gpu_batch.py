@@ -109,11 +109,12 @@ CROWDED_ROUNDS = [
 
 @pytest.mark.parametrize("flags", [0, 2])
 def test_crowded_batch_mixed_and_one_wave_shapes_match_solo(flags):
-    # without the autotuner every round runs the mixed shape: the longest
-    # chains first in the two-wave form while they fit (L = 96, then L = 64 in
-    # pairs), from the first that does not (L = 48) on the one-wave form; with
-    # it the first four rounds time the mixed shape, both one-wave shapes and
-    # the split-merge cadence, and later rounds keep the fastest; every member
+    # without the autotuner every round runs the mixed-longest shape: the
+    # two-wave form only for the longest chain (L = 96), the one-wave form for
+    # the rest; with it the first five rounds time the mixed-longest shape, the
+    # mixed shape (the longest chains first in the two-wave form while they
+    # fit: L = 96, then L = 64 in pairs), both one-wave shapes and the
+    # split-merge cadence, and later rounds keep the fastest; every member
     # stays bit for bit equal to its solo run
     from paper_1707_00919_amd import Batch
     note("crowded batch flags=%d" % flags)
@@ -140,7 +141,7 @@ def test_crowded_batch_mixed_and_one_wave_shapes_match_solo(flags):
     if flags & 2:
         assert forms[0] == {1, 5} and forms[4] == {3, 4}
     else:
-        assert forms[0] == {5} and forms[4] == {4}
+        assert forms[0] == {1} and forms[4] == {4}
     batch.close()
 
 
@@ -287,8 +288,9 @@ def test_batched_workload_full_size_sampled_walkers():
 
 def test_batched_workload_full_size_iterations_match_oracle():
     # the 48 instances at their full sizes in the benchmark's launch form
-    # (graph + autotune: the first round runs the mixed shape, the L = 48 and
-    # L = 64 members in pairs, the second a one-wave shape), two weight
+    # (graph + autotune: the first round runs the mixed-longest shape, the
+    # L = 64 members in pairs, the second the mixed shape, the L = 48 and
+    # L = 64 members in pairs), two weight
     # iterations of one unrecorded and one recorded sweep; every member's
     # histogram and omega bit patterns, and every walker's spins and energy,
     # against the oracle run on all walkers

@@ -12,9 +12,10 @@ Checked for every round against the planner's stated rules:
 * a skipped member gets nothing;
 * when the round fits and the shape is two-wave, every member with a two-wave
   form runs it (in pairs only where single workgroups do not fit);
-* in the mixed shape the two-wave members fit (shares <= CUs, blocks <= 2 per
+* in the mixed shapes the two-wave members fit (shares <= CUs, blocks <= 2 per
   CU), and none of them ranks after a member left one-wave in the order the
-  rule gives (longest chain first, then fewest walkers).
+  rule gives (longest chain first, then fewest walkers); in the mixed-longest
+  shape every two-wave member's chain is the round's longest.
 """
 import os
 import shutil
@@ -58,9 +59,9 @@ int main(int argc, char** argv)
     const int rounds = argc > 1 ? std::atoi(argv[1]) : 20000;
     const uint32_t lds = 160u * 1024u;
     const uint32_t cus_choices[] = {1, 4, 32, 256};
-    const int shapes[] = {kShapeTwoWave, kShapeOneWave, kShapeOneWaveFour, kShapeMixed};
+    const int shapes[] = {kShapeTwoWave, kShapeOneWave, kShapeOneWaveFour, kShapeMixed, kShapeMixedLongest};
     size_t i = 0;
-    uint64_t seen[6] = {0, 0, 0, 0, 0, 0}, fits = 0, single = 0;
+    uint64_t seen[6] = {0, 0, 0, 0, 0, 0}, fits = 0, single = 0, seen_longest[2] = {0, 0};
     for (int round = 0; round < rounds; ++round) {
         const size_t n = below(60);
         const uint32_t cus = cus_choices[below(4)];
@@ -92,6 +93,11 @@ int main(int argc, char** argv)
         for (int shape : shapes) {
             std::vector<uint32_t> form(n, 77u), waves(n, 77u);
             plan_forms(m.data(), n, cus, fit, shape, form.data(), waves.data());
+            const bool mixed = shape == kShapeMixed || shape == kShapeMixedLongest;
+            uint64_t longest = 0;
+            for (i = 0; i < n; ++i)
+                if (m[i].active && fit.share[i] > 0.0)
+                    longest = longest > m[i].chain ? longest : m[i].chain;
             double used = 0.0;
             uint64_t blocks = 0;
             for (i = 0; i < n; ++i) {
@@ -126,12 +132,15 @@ int main(int argc, char** argv)
                 const bool two = f == kFormSplit || f == kFormWideSplit || f == kFormPair;
                 if (shape == kShapeTwoWave && fit.two_wave && fit.share[i] > 0.0 && !r.forced_fast)
                     CHECK(two);
-                if (shape == kShapeMixed && two && fit.share[i] > 0.0) {
+                if (mixed && two && fit.share[i] > 0.0) {
                     used += fit.share[i];
                     blocks += r.blocks;
+                    if (shape == kShapeMixedLongest)
+                        CHECK(r.chain == longest);
+                    ++seen_longest[shape == kShapeMixedLongest];
                 }
             }
-            if (shape == kShapeMixed) {
+            if (mixed) {
                 i = 0;
                 CHECK(used <= (double)cus + 1e-9);
                 CHECK(blocks <= 2ull * cus);
@@ -164,7 +173,8 @@ int main(int argc, char** argv)
     std::printf("ok %d", rounds);
     for (uint64_t c : seen)
         std::printf(" %llu", (unsigned long long)c);
-    std::printf(" %llu %llu\n", (unsigned long long)fits, (unsigned long long)single);
+    std::printf(" %llu %llu %llu %llu\n", (unsigned long long)fits, (unsigned long long)single,
+                (unsigned long long)seen_longest[0], (unsigned long long)seen_longest[1]);
     return 0;
 }
 """
@@ -196,7 +206,10 @@ def test_round_plan_rules_hold_over_random_rounds(fuzz):
     assert words[:2] == ["ok", "20000"]
     seen = [int(w) for w in words[2:8]]
     fits, single = int(words[8]), int(words[9])
+    two_wave_mixed, two_wave_longest = int(words[10]), int(words[11])
     # every form came up, and rounds that fit with single workgroups, only in
-    # pairs, and not at all
+    # pairs, and not at all; both mixed shapes gave some members the two-wave
+    # form, the mixed-longest shape to fewer
     assert all(c > 0 for c in seen), seen
     assert 0 < single < fits < 20000
+    assert 0 < two_wave_longest < two_wave_mixed
