@@ -46,10 +46,10 @@ constexpr uint32_t kGeneric = muca_host::kFormGeneric, kFast = muca_host::kFormF
 bool two_wave_form(uint32_t form) { return form == kSplit || form == kPair || form == kWideSplit; }
 
 // A round's launches are issued longest chains first -- the two-wave groups,
-// then the others, each kind by its longest chain -- and each one after the
-// first behind a wait of this many microseconds more than the one before, long
-// enough for the earlier launches to have placed their workgroups
-// (muca_order.hip).
+// then the others, each kind by its longest chain -- and, in rounds where
+// placement can hold a workgroup back, each one after the first behind a wait
+// of this many microseconds more than the one before, long enough for the
+// earlier launches to have placed their workgroups (muca_order.hip).
 constexpr uint32_t kDispatchDelayUs = 30;
 
 struct Group {
@@ -118,6 +118,8 @@ struct muca_batch {
     // with MUCA_BATCH_GRAPH the host half of a round runs inside the graph, as
     // a host node after the histogram download; its results wait here
     bool host_in_graph = false;
+    // the submitted round's launches start staggered (crowded or paired rounds)
+    bool stagger = false;
     std::vector<muca_info> round_infos;
     int host_rc = MUCA_OK;
     std::string host_err;
@@ -223,13 +225,14 @@ int enqueue_round(muca_batch* b, size_t stage_used, const std::vector<Group>& gr
     const auto* fargs = reinterpret_cast<const muca::FastSweepArgs*>(ds + b->off_fargs);
     const auto* gargs = reinterpret_cast<const muca::SweepArgs*>(ds + b->off_gargs);
     const auto* items = reinterpret_cast<const muca::BatchItem*>(ds + b->off_items);
-    // groups come in dispatch order (muca_batch_submit): each after the first
-    // waits a little longer than the one before
+    // groups come in dispatch order (muca_batch_submit): in a crowded or
+    // paired round each after the first waits a little longer than the one
+    // before
     for (size_t g = 0; g < groups.size(); ++g) {
         const Group& G = groups[g];
         hipStream_t s = b->gstreams[g];
         BATCH_HIP(b, hipStreamWaitEvent(s, b->ev_fork, 0), "hipStreamWaitEvent");
-        if (g > 0)
+        if (g > 0 && b->stagger)
             BATCH_HIP(b, muca::launch_dispatch_delay((uint32_t)g * kDispatchDelayUs, s), "dispatch delay");
         hipError_t e;
         if (G.form == kSplit)
@@ -607,7 +610,11 @@ static int muca_batch_submit_impl(muca_batch* b, const uint32_t* mode, const uin
         groups.push_back(G);
     }
     // dispatch order: two-wave groups first, then the others, each kind by its
-    // longest chain (muca_order.hip)
+    // longest chain (muca_order.hip); the starts are staggered where placement
+    // can hold a workgroup back -- rounds whose two-wave workgroups do not all
+    // fit, and rounds of pair workgroups, each of which needs a whole CU
+    b->stagger = !two_wave || fit.use_pairs;
+    key += b->stagger ? "s" : "u";
     std::stable_sort(groups.begin(), groups.end(), [](const Group& x, const Group& y) {
         const bool tx = two_wave_form(x.form), ty = two_wave_form(y.form);
         return tx != ty ? tx : x.chain > y.chain;

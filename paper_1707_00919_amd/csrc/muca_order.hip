@@ -9,8 +9,9 @@
 // chain plus a long one; among one-wave launches, the same holds for a
 // long-chain launch whose workgroups need much LDS.  The batch runtime
 // therefore issues a round's launches longest chains first (two-wave ones
-// before the others) and puts a wait in front of each later one, a little
-// longer for each, so that workgroups are placed in that order.  Results do
+// before the others) and, in rounds whose two-wave workgroups do not all fit
+// or run in pairs, puts a wait in front of each later one, a little longer
+// for each, so that workgroups are placed in that order.  Results do
 // not depend on it (every workgroup runs the same chains whatever CU it lands
 // on).
 #include <hip/hip_runtime.h>
