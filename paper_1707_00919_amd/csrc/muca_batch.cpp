@@ -49,8 +49,11 @@ bool two_wave_form(uint32_t form) { return form == kSplit || form == kPair || fo
 // then the others, each kind by its longest chain -- and, in rounds where
 // placement can hold a workgroup back, each one after the first behind a wait
 // of this many microseconds more than the one before, long enough for the
-// earlier launches to have placed their workgroups (muca_order.hip).
+// earlier launches to have placed their workgroups (muca_order.hip); from the
+// ninth launch on the wait stays at its eighth step (the shortest chains come
+// last, and their order among themselves hardly matters).
 constexpr uint32_t kDispatchDelayUs = 30;
+constexpr uint32_t kDispatchSteps = 8;
 
 struct Group {
     uint32_t L = 0;
@@ -233,7 +236,8 @@ int enqueue_round(muca_batch* b, size_t stage_used, const std::vector<Group>& gr
         hipStream_t s = b->gstreams[g];
         BATCH_HIP(b, hipStreamWaitEvent(s, b->ev_fork, 0), "hipStreamWaitEvent");
         if (g > 0 && b->stagger)
-            BATCH_HIP(b, muca::launch_dispatch_delay((uint32_t)g * kDispatchDelayUs, s), "dispatch delay");
+            BATCH_HIP(b, muca::launch_dispatch_delay((uint32_t)std::min<size_t>(g, kDispatchSteps) * kDispatchDelayUs, s),
+                      "dispatch delay");
         hipError_t e;
         if (G.form == kSplit)
             e = muca::launch_split_batch(G.L, fargs, items + G.first_item, G.nitems, s);
