@@ -647,6 +647,31 @@ hipError_t hipGraphExecDestroy(hipGraphExec_t exec)
 // Reported by the driver at exit: frees that had to wait for queued work.
 uint64_t cpu_hip_free_waits() { return g_free_waits.load(); }
 
+// The launches of batched rounds as they are issued (host order): for a wait,
+// form is -1 and value the microseconds; for a batched sweep, form is the
+// kernel form (muca_info::kernel_variant) and value L.
+struct CpuHipLaunch {
+    const void* stream;
+    int form;
+    uint32_t value;
+};
+namespace {
+std::mutex g_log_m;
+std::vector<CpuHipLaunch> g_log;
+void log_launch(hipStream_t s, int form, uint32_t value)
+{
+    std::lock_guard<std::mutex> lk(g_log_m);
+    g_log.push_back(CpuHipLaunch{s, form, value});
+}
+}  // namespace
+std::vector<CpuHipLaunch> cpu_hip_take_launch_log()
+{
+    std::lock_guard<std::mutex> lk(g_log_m);
+    std::vector<CpuHipLaunch> out;
+    out.swap(g_log);
+    return out;
+}
+
 // -- stand-in kernels -------------------------------------------------------
 
 namespace muca {
@@ -812,6 +837,7 @@ hipError_t launch_init(const InitArgs& a, hipStream_t s)
 
 hipError_t launch_dispatch_delay(uint32_t microseconds, hipStream_t s)
 {
+    log_launch(s, -1, microseconds);
     if (microseconds)
         submit(resolve(s), [microseconds] {
             std::this_thread::sleep_for(std::chrono::microseconds(microseconds));
@@ -853,6 +879,7 @@ hipError_t launch_sweep_range(const RangeArgs& a, hipStream_t s)
 hipError_t launch_sweep_batch(uint32_t L, const SweepArgs* args, const BatchItem* items, uint32_t nitems,
                               hipStream_t s)
 {
+    log_launch(s, 0, L);
     batch(L, args, items, nitems, s, kTableU64x4, 1, false, "generic batch: block past the walkers");
     return hipSuccess;
 }
@@ -861,12 +888,14 @@ hipError_t launch_fast_batch(uint32_t L, uint32_t G, const FastSweepArgs* args, 
 {
     if (G != 1 && G != 2 && G != 4)
         return hipErrorInvalidValue;
+    log_launch(s, 1, L);
     batch(L, args, items, nitems, s, kTableU32x5, G, false, "one-wave batch: first block past the walkers");
     return hipSuccess;
 }
 hipError_t launch_wide_batch(uint32_t L, const FastSweepArgs* args, const BatchItem* items, uint32_t nitems,
                              hipStream_t s)
 {
+    log_launch(s, 3, L);
     batch(L, args, items, nitems, s, kTableU32x8, 1, false, "wide batch: block past the walkers");
     return hipSuccess;
 }
@@ -875,18 +904,21 @@ hipError_t launch_pair_batch(uint32_t L, const FastSweepArgs* args, const BatchI
 {
     if (!pair_sweep_supported(L))
         return hipErrorInvalidValue;
+    log_launch(s, 5, L);
     batch(L, args, items, nitems, s, kTableU32x5, 2, false, "pair batch: first block past the walkers");
     return hipSuccess;
 }
 hipError_t launch_split_batch(uint32_t L, const FastSweepArgs* args, const BatchItem* items, uint32_t nitems,
                               hipStream_t s)
 {
+    log_launch(s, 2, L);
     batch(L, args, items, nitems, s, kTableU32x5, 1, false, "two-wave batch: block past the walkers");
     return hipSuccess;
 }
 hipError_t launch_wide_split_batch(uint32_t L, const FastSweepArgs* args, const BatchItem* items,
                                    uint32_t nitems, hipStream_t s)
 {
+    log_launch(s, 4, L);
     batch(L, args, items, nitems, s, kTableU32x8, 1, false, "wide two-wave batch: block past the walkers");
     return hipSuccess;
 }

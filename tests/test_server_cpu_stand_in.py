@@ -11,6 +11,8 @@ workload's own request stream (muca_inputs.serving_requests: Poisson arrivals,
 L in {16, 24, 32, 48, 64}, 1024-16384 walkers) through the server, time-scaled,
 and checks every result (status, iterations, attempts, ln g finite) and, for a
 sample, that ln g is bit-identical to the same request solved alone.
+tests/cpu_hip/launch_order.cpp checks the order and staggering of a batched
+round's launches on the same stand-in.
 
 Frees do not wait for queued work here (CPU_HIP_FREE_NOWAIT=1), so that work
 still queued on freed memory would trip AddressSanitizer or the range checks.
@@ -26,15 +28,14 @@ import pytest
 ROOT = os.path.abspath(os.path.join(os.path.dirname(__file__), ".."))
 CSRC = os.path.join(ROOT, "paper_1707_00919_amd", "csrc")
 STAND_IN = os.path.join(ROOT, "tests", "cpu_hip")
-SOURCES = [os.path.join(CSRC, f) for f in ("muca_runtime.cpp", "muca_batch.cpp", "muca_server.cpp",
-                                           "muca_host_math.cpp")] + \
-          [os.path.join(STAND_IN, f) for f in ("cpu_hip.cpp", "served_stream.cpp")]
+LIBRARY = [os.path.join(CSRC, f) for f in ("muca_runtime.cpp", "muca_batch.cpp", "muca_server.cpp",
+                                           "muca_host_math.cpp")] + [os.path.join(STAND_IN, "cpu_hip.cpp")]
 
 FIFO, SMALLEST_FIRST = 0, 1
 GRAPH, AUTOTUNE = 1, 2
 
 
-def _build(tmp, name, sanitize):
+def _build(tmp, name, sanitize, driver="served_stream.cpp"):
     gxx = shutil.which("g++")
     if gxx is None:
         pytest.skip("no g++")
@@ -43,7 +44,8 @@ def _build(tmp, name, sanitize):
            "-Wno-attributes", "-pthread", "-I" + STAND_IN, "-I" + os.path.join(ROOT, "include"), "-I" + CSRC]
     if sanitize != "thread":
         cmd.append("-fno-sanitize-recover=all")
-    r = subprocess.run(cmd + SOURCES + ["-o", exe, "-lm"], capture_output=True, text=True)
+    sources = LIBRARY + [os.path.join(STAND_IN, driver)]
+    r = subprocess.run(cmd + sources + ["-o", exe, "-lm"], capture_output=True, text=True)
     if r.returncode != 0 and "san" in (r.stderr or "").lower() and "cannot find" in (r.stderr or "").lower():
         pytest.skip("sanitizer runtime not available: " + r.stderr[-200:])
     assert r.returncode == 0, r.stderr[-3000:]
@@ -106,3 +108,14 @@ def test_served_stream_head_under_tsan(tsan, streams):
     """Graph rounds end in a host node on a stream worker thread while the
     driver thread admits, launches and collects other lanes."""
     _run(tsan, streams["head"], GRAPH, FIFO, solo_every=50, env={"TSAN_OPTIONS": "halt_on_error=1"})
+
+
+def test_batched_launch_order(tmp_path):
+    """A batched round issues its two-wave launches first, each kind by its
+    longest chain, and staggers the starts (30 us more per launch) in crowded
+    and paired rounds only; with and without the captured graph
+    (tests/cpu_hip/launch_order.cpp)."""
+    exe = _build(tmp_path, "launch_order", "address,undefined", driver="launch_order.cpp")
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=300, env=dict(os.environ, CPU_HIP_RATE="0"))
+    assert r.returncode == 0, (r.stdout + r.stderr)[-3000:]
+    assert r.stdout.strip().splitlines()[-1] == "ok"
