@@ -1,6 +1,7 @@
 """Host-side pieces of bench.py that need no GPU: the percentile rule, the
-exact tables it reads, the scaled weights of its L = 128 profile pass, and the
-refusal of more than one GPU."""
+exact tables it reads, the scaled weights of its L = 128 profile pass, the
+refusal of more than one GPU, and the committed counter summaries it reads
+(used only while they were taken on the current kernel sources)."""
 import math
 import os
 import subprocess
@@ -53,3 +54,32 @@ def test_more_than_one_gpu_is_refused():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_committed_summaries_match_the_current_kernel_sources():
+    # the traffic and the chain instruction count in the benchmark line come
+    # from profiles taken on the sources in the tree
+    bytes_, note = bench.traffic_per_launch()
+    assert bytes_ is not None and bytes_ > 0, note + " -- re-take the counter profiles on the current sources"
+    roof, note = bench.chain_roof(4.0e11, 16384)
+    assert roof is not None, note + " -- re-count the chain instructions on the current sources"
+    assert roof["chain_waves"] == 256
+    # 256 waves x 64 lanes x 2.4 GHz / (4 clocks x instructions per attempt)
+    assert math.isclose(roof["peak"], 256 * 64 * 2.4e9 / (4 * roof["chain_instructions_per_attempt"]))
+
+
+def test_summaries_of_other_kernel_sources_are_not_used(tmp_path, monkeypatch):
+    stale_traffic = tmp_path / "traffic.txt"
+    stale_traffic.write_text("kernel_source_sha256_16 = 0000000000000000\nhbm_bytes_per_launch = 123\n")
+    stale_chain = tmp_path / "chain.md"
+    stale_chain.write_text("kernel_source_sha256_16 = 0000000000000000\nchain_instructions_per_attempt = 18\n")
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(stale_traffic))
+    monkeypatch.setattr(bench, "CHAIN_FILE", str(stale_chain))
+    bytes_, note = bench.traffic_per_launch()
+    assert bytes_ is None and "not used" in note
+    roof, note = bench.chain_roof(4.0e11, 16384)
+    assert roof is None and "not used" in note
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(tmp_path / "missing.txt"))
+    bytes_, note = bench.traffic_per_launch()
+    assert bytes_ is None and "missing" in note
+
